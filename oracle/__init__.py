@@ -1,0 +1,20 @@
+"""CPU oracle for the silhouette hot path: plain, slow, float64.
+
+TEST INFRASTRUCTURE ONLY.  It is imported by the tests, by the smoke check
+and by the benchmark's CPU-baseline leg, and by nothing on the product path.
+It shares no code, header or table with the HIP implementation.
+
+Modules:
+  philox      Philox4x32-10 and the 53-bit uniform built from it.
+  distance    the four distances of the experiments, float64.
+  silhouette  exact silhouette, Phase 1 / Phase 2 of Algorithm 1, the
+              uniform-sampling variant and the global mean (Eq. 9).
+
+Parity status: every function here is pinned by tests in tests/test_oracle_*.py
+against values the paper prints, closed forms, brute force or invariants; none
+is "parity unpinned".
+"""
+from .distance import CANB, COS, EUCL, MANH, dist_matrix, dist_to_point, metric_id  # noqa: F401
+from .philox import STREAM_F0, STREAM_PPS, STREAM_UNI, philox4x32_10, uniform53  # noqa: F401
+from .silhouette import (cluster_members, default_t, estimate, exact, global_mean,  # noqa: F401
+                         pps_silhouette, sample, scores_from_weights)

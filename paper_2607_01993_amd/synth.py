@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs (points + cluster labels) shared by the tests, the
+benchmark and the CPU oracle's callers.
+
+This module only draws data.  It contains none of the silhouette arithmetic
+(no distances, no sampling probabilities, no estimators): the same arrays are
+handed to the HIP path and to the FP64 oracle, which then compute
+independently.
+
+The paper evaluates on public UCI/SNAP datasets (n from hundreds to 6.4M,
+z = 2..78, k = 2..20, Section 5.1.1, Table 2) clustered by k-means/k-medoids.
+Those files are not available here; the generators below produce blob data of
+the same shape family, with the recipes stated in each docstring.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "zipf_sizes", "gaussian_blobs", "vmf_blobs", "config_small", "config_zipf_gauss",
+    "config_vmf_cos", "tiny_case",
+]
+
+
+def zipf_sizes(n: int, k: int, s: float = 1.1) -> np.ndarray:
+    """Cluster sizes proportional to r^-s (r = 1..k), rounded with the
+    largest-remainder rule so that they sum to exactly n (every size >= 1)."""
+    w = np.arange(1, k + 1, dtype=np.float64) ** (-s)
+    raw = n * w / w.sum()
+    base = np.floor(raw).astype(np.int64)
+    rem = n - int(base.sum())
+    order = np.argsort(-(raw - base), kind="stable")
+    base[order[:rem]] += 1
+    base = np.maximum(base, 1)
+    # a size forced up to 1 is paid for by the largest cluster
+    base[0] -= int(base.sum()) - n
+    return base
+
+
+def _shuffle(rng, X, labels):
+    perm = rng.permutation(X.shape[0])
+    return np.ascontiguousarray(X[perm]), np.ascontiguousarray(labels[perm])
+
+
+def gaussian_blobs(n: int, d: int, k: int, seed: int, sizes=None, sigma=(1.0, 1.0),
+                   center_range: float = 10.0, shuffle: bool = True):
+    """Isotropic Gaussian blobs.
+
+    centers ~ U[-center_range, center_range]^d; cluster j has standard
+    deviation sigma_j ~ U[sigma[0], sigma[1]]; point = center + sigma_j*N(0, I).
+    Returns (X float32 [n, d] row-major, labels int32 [n]); rows are shuffled by
+    a seeded permutation so that clusters are interleaved in memory.
+    """
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sizes = np.full(k, n // k, dtype=np.int64)
+        sizes[: n - int(sizes.sum())] += 1
+    sizes = np.asarray(sizes, dtype=np.int64)
+    assert int(sizes.sum()) == n and sizes.shape[0] == k
+    centers = rng.uniform(-center_range, center_range, size=(k, d))
+    sig = rng.uniform(sigma[0], sigma[1], size=k)
+    X = np.empty((n, d), dtype=np.float32)
+    labels = np.empty(n, dtype=np.int32)
+    o = 0
+    for j in range(k):
+        m = int(sizes[j])
+        X[o:o + m] = (centers[j] + sig[j] * rng.standard_normal((m, d))).astype(np.float32)
+        labels[o:o + m] = j
+        o += m
+    if shuffle:
+        X, labels = _shuffle(rng, X, labels)
+    return X, labels
+
+
+def _wood_vmf(rng, mu: np.ndarray, kappa: float, m: int) -> np.ndarray:
+    """m draws from the von Mises-Fisher distribution on S^{d-1} with mean
+    direction mu and concentration kappa (Wood, 1994, rejection sampler for
+    the component along mu, uniform direction in the orthogonal complement)."""
+    d = mu.shape[0]
+    dm1 = d - 1.0
+    b = (-2.0 * kappa + np.sqrt(4.0 * kappa * kappa + dm1 * dm1)) / dm1
+    x0 = (1.0 - b) / (1.0 + b)
+    c = kappa * x0 + dm1 * np.log(1.0 - x0 * x0)
+    w = np.empty(m)
+    got = 0
+    while got < m:
+        need = m - got
+        batch = int(need * 1.3) + 16
+        z = rng.beta(dm1 / 2.0, dm1 / 2.0, size=batch)
+        ww = (1.0 - (1.0 + b) * z) / (1.0 - (1.0 - b) * z)
+        u = rng.uniform(size=batch)
+        ok = kappa * ww + dm1 * np.log(1.0 - x0 * ww) - c >= np.log(u)
+        acc = ww[ok][:need]
+        w[got:got + acc.shape[0]] = acc
+        got += acc.shape[0]
+    v = rng.standard_normal((m, d))
+    v -= np.outer(v @ mu, mu)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return w[:, None] * mu[None, :] + np.sqrt(np.maximum(0.0, 1.0 - w * w))[:, None] * v
+
+
+def vmf_blobs(n: int, d: int, k: int, seed: int, kappa: float = 50.0, sizes=None,
+              shuffle: bool = True):
+    """Directional blobs: mean directions uniform on S^{d-1}; cluster j draws
+    from vMF(mu_j, kappa) (Wood's sampler); rows are L2-normalised in float64
+    before the cast to float32."""
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sizes = zipf_sizes(n, k)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    X = np.empty((n, d), dtype=np.float32)
+    labels = np.empty(n, dtype=np.int32)
+    o = 0
+    for j in range(k):
+        mu = rng.standard_normal(d)
+        mu /= np.linalg.norm(mu)
+        m = int(sizes[j])
+        P = _wood_vmf(rng, mu, kappa, m)
+        P /= np.linalg.norm(P, axis=1, keepdims=True)
+        X[o:o + m] = P.astype(np.float32)
+        labels[o:o + m] = j
+        o += m
+    if shuffle:
+        X, labels = _shuffle(rng, X, labels)
+    return X, labels
+
+
+def config_small():
+    """n=2,000, d=8, k=4 equal Gaussian blobs (sigma=1, centers U[-10,10]^8), seed 0."""
+    return gaussian_blobs(2000, 8, 4, seed=0)
+
+
+def config_zipf_gauss(n: int = 1_000_000, d: int = 32, k: int = 16, seed: int = 1):
+    """n=1e6, d=32, k=16 Gaussian blobs, Zipf(1.1) sizes, sigma_j ~ U[0.5, 2], seed 1."""
+    return gaussian_blobs(n, d, k, seed=seed, sizes=zipf_sizes(n, k), sigma=(0.5, 2.0))
+
+
+def config_vmf_cos(n: int = 4_000_000, d: int = 128, k: int = 64, seed: int = 2):
+    """n=4e6, d=128, k=64 vMF(kappa=50) blobs with Zipf(1.1) sizes, unit rows, seed 2."""
+    return vmf_blobs(n, d, k, seed=seed, kappa=50.0, sizes=zipf_sizes(n, k))
+
+
+def tiny_case(n: int, d: int, k: int, seed: int, sigma=(0.5, 2.0), sizes=None):
+    """Small Gaussian-blob case for parity tests (uneven sizes by default)."""
+    if sizes is None:
+        rng = np.random.default_rng(seed + 7919)
+        w = rng.uniform(0.3, 1.0, size=k)
+        sizes = np.maximum(1, np.floor(n * w / w.sum()).astype(np.int64))
+        sizes[0] += n - int(sizes.sum())
+    return gaussian_blobs(n, d, k, seed=seed, sizes=sizes, sigma=sigma)
