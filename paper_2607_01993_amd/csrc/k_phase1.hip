@@ -1,0 +1,349 @@
+// Phase 1 of Algorithm 1 (PPS sampling) and the uniform Poisson sampler of
+// Section 4.1.3, all decisions in float64.
+//
+// This file is compiled with -ffp-contract=off: every distance below is one
+// rounding per elementary operation, coordinates accumulated in increasing
+// order, so its value does not depend on how the compiler schedules it.
+#include "device_common.hpp"
+#include "silh_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace silh {
+
+// Distances from x (float32 row, promoted exactly) to NE float64 rows y[e]
+// (row stride d), for the metric M.  Up to EB rows at a time.
+template <int M, int EB>
+__device__ __forceinline__ void dist64_multi(const float* __restrict__ x, int d,
+                                             const double* __restrict__ y, int ne, double out[EB]) {
+  double acc[EB], dot[EB], ny2[EB];
+  double nx2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    acc[e] = 0.0;
+    dot[e] = 0.0;
+    ny2[e] = 0.0;
+  }
+  for (int c = 0; c < d; ++c) {
+    const double xc = (double)x[c];
+    if (M == kCos) nx2 = nx2 + xc * xc;
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      if (e < ne) {
+        const double yc = y[(size_t)e * d + c];
+        if (M == kEucl) {
+          const double df = xc - yc;
+          acc[e] = acc[e] + df * df;
+        } else if (M == kManh) {
+          acc[e] = acc[e] + fabs(xc - yc);
+        } else if (M == kCanb) {
+          const double num = fabs(xc - yc);
+          const double den = fabs(xc) + fabs(yc);
+          const double term = den > 0.0 ? num / den : 0.0;
+          acc[e] = acc[e] + term;
+        } else {
+          dot[e] = dot[e] + xc * yc;
+          ny2[e] = ny2[e] + yc * yc;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    if (M == kEucl) {
+      out[e] = __dsqrt_rn(acc[e]);
+    } else if (M == kCos) {
+      const double den = __dsqrt_rn(nx2) * __dsqrt_rn(ny2[e]);
+      const double sim = den > 0.0 ? dot[e] / den : 0.0;
+      double v = 1.0 - sim;
+      v = v < 0.0 ? 0.0 : (v > 2.0 ? 2.0 : v);
+      out[e] = v;
+    } else {
+      out[e] = acc[e];
+    }
+  }
+}
+
+constexpr int kEB = 8;  // initial-sample rows handled together
+
+// ----------------------------------------------------------------------------
+// F^0 draw: sorted position i, element g = perm[i] of cluster j; kept when
+// |C_j| > t and U(seed, g, 0) < q_j.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_f0_flag(const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ slab, int n,
+                                                 const int32_t* __restrict__ csize,
+                                                 const double* __restrict__ q, int64_t t,
+                                                 uint64_t seed, int32_t* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = slab[i];
+  int32_t f = 0;
+  if ((int64_t)csize[j] > t) f = uniform53(seed, (uint64_t)perm[i], kStreamF0) < q[j] ? 1 : 0;
+  flag[i] = f;
+}
+
+void launch_f0_flag(hipStream_t st, const int32_t* perm, const int32_t* slab, int n,
+                    const int32_t* csize, const double* q, int64_t t, uint64_t seed, int32_t* flag) {
+  hipLaunchKernelGGL(k_f0_flag, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, n, csize,
+                     q, t, seed, flag);
+}
+
+__global__ __launch_bounds__(256) void k_f0_pack(const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ slab,
+                                                 const int32_t* __restrict__ flag,
+                                                 const int32_t* __restrict__ pos, int n,
+                                                 const float* __restrict__ X, int d,
+                                                 int64_t* __restrict__ f0_gid,
+                                                 int32_t* __restrict__ f0_cl, double* __restrict__ f0X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  const int dst = pos[i];
+  const int g = perm[i];
+  f0_gid[dst] = g;
+  f0_cl[dst] = slab[i];
+  const float* xr = X + (size_t)g * d;
+  double* yr = f0X + (size_t)dst * d;
+  for (int c = 0; c < d; ++c) yr[c] = (double)xr[c];
+}
+
+void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
+                    const int32_t* pos, int n, const float* X, int d, int64_t* f0_gid,
+                    int32_t* f0_cl, double* f0X) {
+  hipLaunchKernelGGL(k_f0_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos,
+                     n, X, d, f0_gid, f0_cl, f0X);
+}
+
+// ----------------------------------------------------------------------------
+// W(e_bar) = sum_{e' in C_j} d(e_bar, e') (Algorithm 1, Phase 1).  A work item
+// covers up to kWChunk consecutive members of one cluster; its block writes
+// one partial sum per initial element (per-thread sums in member order, then
+// a fixed-order block reduction).
+// item layout: [cluster, begin, end, f0_begin, f0_count, partial_base]
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ items,
+                                                   const int32_t* __restrict__ perm,
+                                                   const float* __restrict__ X, int d,
+                                                   const double* __restrict__ f0X,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int32_t* it = items + (size_t)blockIdx.x * 6;
+  const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
+  for (int e0 = 0; e0 < f0n; e0 += kEB) {
+    const int ne = f0n - e0 < kEB ? f0n - e0 : kEB;
+    double acc[kEB];
+#pragma unroll
+    for (int e = 0; e < kEB; ++e) acc[e] = 0.0;
+    for (int r = begin + threadIdx.x; r < end; r += 256) {
+      const float* xr = X + (size_t)perm[r] * d;
+      double dv[kEB];
+      dist64_multi<M, kEB>(xr, d, f0X + (size_t)(f0b + e0) * d, ne, dv);
+#pragma unroll
+      for (int e = 0; e < kEB; ++e) acc[e] = acc[e] + dv[e];
+    }
+#pragma unroll
+    for (int e = 0; e < kEB; ++e) {
+      if (e < ne) {  // ne is uniform over the block
+        const double tot = block_sum_f64<256>(acc[e], sh);
+        if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
+      }
+    }
+  }
+}
+
+void launch_w_partial(hipStream_t st, int metric, const int32_t* items, int nitems,
+                      const int32_t* perm, const float* X, int d, const double* f0X, double* partial) {
+  if (nitems <= 0) return;
+  switch (metric) {
+    case kEucl:
+      hipLaunchKernelGGL(k_w_partial<kEucl>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
+      break;
+    case kCos:
+      hipLaunchKernelGGL(k_w_partial<kCos>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
+      break;
+    case kManh:
+      hipLaunchKernelGGL(k_w_partial<kManh>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
+      break;
+    default:
+      hipLaunchKernelGGL(k_w_partial<kCanb>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
+      break;
+  }
+}
+
+// W(e_bar): sum of its cluster's item partials, in item order.
+__global__ __launch_bounds__(256) void k_w_final(const int32_t* __restrict__ f0_cl, int F0,
+                                                 const int32_t* __restrict__ f0_off,
+                                                 const int32_t* __restrict__ citem_first,
+                                                 const int32_t* __restrict__ citem_count,
+                                                 const int32_t* __restrict__ items,
+                                                 const double* __restrict__ partial,
+                                                 double* __restrict__ W) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F0) return;
+  const int j = f0_cl[i];
+  const int local = i - f0_off[j];
+  const int first = citem_first[j], cnt = citem_count[j];
+  double s = 0.0;
+  for (int q = 0; q < cnt; ++q) s = s + partial[items[(size_t)(first + q) * 6 + 5] + local];
+  W[i] = s;
+}
+
+void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off,
+                    const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
+                    const double* partial, double* W) {
+  if (F0 <= 0) return;
+  hipLaunchKernelGGL(k_w_final, dim3((int)ceil_div(F0, 256)), dim3(256), 0, st, f0_cl, F0, f0_off,
+                     citem_first, citem_count, items, partial, W);
+}
+
+// ----------------------------------------------------------------------------
+// gamma_e, p_e and the final Poisson draw (PPS), or the uniform rate t/|C_j|.
+// Clusters with |C_j| <= t are taken whole with p = 1.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __restrict__ perm,
+                                              const int32_t* __restrict__ slab, int n,
+                                              const float* __restrict__ X, int d,
+                                              const int32_t* __restrict__ csize, int64_t t,
+                                              uint64_t seed, const int32_t* __restrict__ f0_off,
+                                              const double* __restrict__ f0X,
+                                              const double* __restrict__ W,
+                                              double* __restrict__ p_gid, int32_t* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int g = perm[i];
+  const int j = slab[i];
+  const int64_t m = csize[j];
+  double p;
+  int32_t sel;
+  if (m <= t) {
+    p = 1.0;
+    sel = 1;
+  } else if (sampler == 1) {
+    p = (double)t / (double)m;
+    p = p < 1.0 ? p : 1.0;
+    sel = uniform53(seed, (uint64_t)g, kStreamUNI) < p ? 1 : 0;
+  } else {
+    double gam = 1.0 / (double)m;
+    const int fb = f0_off[j], fe = f0_off[j + 1];
+    const float* xr = X + (size_t)g * d;
+    for (int e0 = fb; e0 < fe; e0 += kEB) {
+      const int ne = fe - e0 < kEB ? fe - e0 : kEB;
+      double dv[kEB];
+      dist64_multi<M, kEB>(xr, d, f0X + (size_t)e0 * d, ne, dv);
+#pragma unroll
+      for (int e = 0; e < kEB; ++e) {
+        if (e < ne) {
+          const double w = W[e0 + e];
+          if (w > 0.0) {
+            const double r = dv[e] / w;
+            gam = r > gam ? r : gam;
+          }
+        }
+      }
+    }
+    p = (double)t * gam;
+    p = p < 1.0 ? p : 1.0;
+    sel = uniform53(seed, (uint64_t)g, kStreamPPS) < p ? 1 : 0;
+  }
+  p_gid[g] = p;
+  flag[i] = sel;
+}
+
+void launch_draw(hipStream_t st, int metric, int sampler, const int32_t* perm, const int32_t* slab,
+                 int n, const float* X, int d, const int32_t* csize, int64_t t, uint64_t seed,
+                 const int32_t* f0_off, const double* f0X, const double* W, double* p_gid,
+                 int32_t* flag) {
+  const dim3 g((int)ceil_div(n, 256)), b(256);
+  switch (metric) {
+    case kEucl:
+      hipLaunchKernelGGL(k_draw<kEucl>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
+      break;
+    case kCos:
+      hipLaunchKernelGGL(k_draw<kCos>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
+      break;
+    case kManh:
+      hipLaunchKernelGGL(k_draw<kManh>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
+      break;
+    default:
+      hipLaunchKernelGGL(k_draw<kCanb>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
+      break;
+  }
+}
+
+// exact silhouette: every element kept with p = 1
+__global__ __launch_bounds__(256) void k_fill_all(const int32_t* __restrict__ perm, int n,
+                                                  double* __restrict__ p_gid, int32_t* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p_gid[perm[i]] = 1.0;
+  flag[i] = 1;
+}
+
+void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, int32_t* flag) {
+  hipLaunchKernelGGL(k_fill_all, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, n, p_gid, flag);
+}
+
+// ----------------------------------------------------------------------------
+// Sample packing: cluster-blocked rows padded to kSamplePad (padding rows have
+// weight 0 and zero coordinates), weight w = 1/p in float32, and the unpadded
+// id list for inspection.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
+                                              const int32_t* __restrict__ slab,
+                                              const int32_t* __restrict__ flag,
+                                              const int32_t* __restrict__ pos, int n,
+                                              const float* __restrict__ X, int d, int DM,
+                                              const double* __restrict__ p_gid,
+                                              const int32_t* __restrict__ s_off,
+                                              const int32_t* __restrict__ sp_off, int mode,
+                                              int64_t* __restrict__ gid_view,
+                                              int32_t* __restrict__ gid_pk, float* __restrict__ w32,
+                                              float* __restrict__ aux32, float* __restrict__ Y32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  const int g = perm[i];
+  const int j = slab[i];
+  const int ps = pos[i];
+  const int dst = sp_off[j] + (ps - s_off[j]);
+  gid_view[ps] = g;
+  gid_pk[dst] = g;
+  w32[dst] = (float)(1.0 / p_gid[g]);
+  const float* xr = X + (size_t)g * d;
+  float* yr = Y32 + (size_t)dst * DM;
+  double scale = 1.0;
+  if (mode == 1) {
+    double s2 = 0.0;
+    for (int c = 0; c < d; ++c) s2 = s2 + (double)xr[c] * (double)xr[c];
+    scale = s2 > 0.0 ? 1.0 / __dsqrt_rn(s2) : 0.0;
+    aux32[dst] = s2 > 0.0 ? 0.0f : 0.5f;
+  }
+  for (int c = 0; c < DM; ++c) yr[c] = c < d ? (float)((double)xr[c] * scale) : 0.0f;
+}
+
+void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
+                 const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
+                 const int32_t* s_off, const int32_t* sp_off, int mode, int64_t* gid_view,
+                 int32_t* gid_pk, float* w32, float* aux32, float* Y32) {
+  hipLaunchKernelGGL(k_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos, n,
+                     X, d, DM, p_gid, s_off, sp_off, mode, gid_view, gid_pk, w32, aux32, Y32);
+}
+
+// ----------------------------------------------------------------------------
+// diagnostics: the uniforms themselves
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_uniform(uint64_t seed, int64_t gid0, int64_t count,
+                                                 uint32_t stream_id, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = uniform53(seed, (uint64_t)(gid0 + i), stream_id);
+}
+
+void launch_uniform(hipStream_t st, uint64_t seed, int64_t gid0, int64_t count, uint32_t stream_id,
+                    double* out) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_uniform, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, st, seed, gid0,
+                     count, stream_id, out);
+}
+
+}  // namespace silh

@@ -1,0 +1,427 @@
+// Phase 2 of Algorithm 1 on the matrix cores (gfx950 MFMA), for the
+// Euclidean and cosine distances:
+//   W_hat_{C_j}(e) = sum_{e' in F_j} w_{e'} d(e, e'),  w = 1/p,
+// then a_hat, b_hat, s_hat (Eq. 5) and per-block float64 partials of the sum
+// of s_hat (for Eq. 9).
+//
+// Both distances are evaluated as a squared difference of centred points,
+//   |x~ - y~|^2 = |x~|^2 + |y~|^2 - 2 x~.y~ ,   x~ = x - mu_j,  y~ = y - mu_j,
+// where mu_j is a centre of cluster j's sample (the mean of its first samples)
+// and x, y are the raw rows (Euclidean) or the rows scaled to unit length
+// (cosine, where 1 - x^.y^ = |x^ - y^|^2 / 2).  The translation leaves every
+// distance unchanged but keeps the operands small near cluster j, so the
+// expansion does not cancel for near pairs, in float32 or in bf16.  The dot
+// product runs on the MFMA units; the two squared norms ride along as extra
+// contraction columns (split into three bf16 pieces in the bf16 path), so the
+// accumulator leaves the MFMA holding the squared distance itself:
+//   Euclidean:  d = sqrt(|c|)
+//   cosine:     d = med3(c, 0, 2) with c = |x~ - y~|^2 / 2 + u_x + u_y
+//               (u = 0.5 for a zero vector, else 0, which makes d = 1 there).
+//
+// Tile mapping (v_mfma_f32_32x32x{2f32,16_bf16}): a wave owns 32 elements (the
+// A operand rows); each 32-column tile is 32 samples of one cluster (the B
+// operand columns, cluster blocks padded to 32 with zero-weight rows).  Lane l
+// holds sample column l%32 of the accumulator and 16 element rows, so its
+// weight is a single register; per-row partial sums stay in registers across
+// the cluster's tiles and are combined across the 32 columns by a
+// transpose-reduction (5 exchange steps) when the cluster ends or every kFold
+// tiles, then added in float64.  The contraction order is free, so each lane
+// feeds the MFMA a contiguous half of the (augmented) row: half h = l/32 of
+// the row holds logical coordinates [h*HALF, (h+1)*HALF).
+#include "device_common.hpp"
+#include "silh_internal.hpp"
+
+namespace silh {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
+constexpr int kCenterRows = 1024;
+
+__host__ __device__ constexpr int round_up_c(int a, int b) { return (a + b - 1) / b * b; }
+
+template <int P, int DM>
+struct MCfg {
+  static constexpr int AUG = P == 0 ? 2 : 6;
+  static constexpr int KP = P == 0 ? round_up_c(DM + AUG, 4) : round_up_c(DM + AUG, 16);
+  static constexpr int HALF = KP / 2;
+  static constexpr int NSTEP = P == 0 ? HALF : HALF / 8;
+};
+
+int mfma_kp(int prec, int DM) {
+  if (prec == 0) return round_up_c(DM + 2, 4);
+  return round_up_c(DM + 6, 16);
+}
+
+__device__ __forceinline__ float q_bf16(float v) { return (float)(__bf16)v; }
+
+// split v into three bf16 pieces whose sum is v to about 2^-24 relative
+__device__ __forceinline__ void split3(float v, float& h, float& m, float& l) {
+  h = q_bf16(v);
+  const float r1 = v - h;
+  m = q_bf16(r1);
+  l = q_bf16(r1 - m);
+}
+
+// ----------------------------------------------------------------------------
+// centre of each cluster's sample: mean of its first kCenterRows rows of Y32
+// (float64 sums; any point of the cluster would do, the mean keeps the
+// centred operands smallest)
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_center(const float* __restrict__ Y32, int DM,
+                                                const int32_t* __restrict__ sp_off,
+                                                const int32_t* __restrict__ cnt,
+                                                float* __restrict__ mu) {
+  const int j = blockIdx.x;
+  const int m = cnt[j] < kCenterRows ? cnt[j] : kCenterRows;
+  const int base = sp_off[j];
+  for (int c = threadIdx.x; c < DM; c += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < m; ++r) s += (double)Y32[(size_t)(base + r) * DM + c];
+    mu[(size_t)j * DM + c] = m > 0 ? (float)(s / m) : 0.0f;
+  }
+}
+
+void launch_center(hipStream_t st, const float* Y32, int DM, const int32_t* sp_off, const int32_t* cnt,
+                   int k, float* mu) {
+  hipLaunchKernelGGL(k_center, dim3(k), dim3(256), 0, st, Y32, DM, sp_off, cnt, mu);
+}
+
+// ----------------------------------------------------------------------------
+// B operand rows: [ -2 alpha y~_q (DM) | augmentation | 0 ... ] with
+// alpha = 1 (Euclidean) or 1/2 (cosine); y~_q = y~ rounded to the input
+// precision; the augmentation carries alpha |y~_q|^2 + u_y.  Padding rows are
+// all zero.
+// ----------------------------------------------------------------------------
+template <int M, int P, int DM>
+__global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32,
+                                                   const float* __restrict__ aux,
+                                                   const int32_t* __restrict__ sp_off,
+                                                   const int32_t* __restrict__ cnt, int k,
+                                                   const float* __restrict__ mu, int S_pad,
+                                                   void* __restrict__ Ym) {
+  using C = MCfg<P, DM>;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S_pad) return;
+  // cluster of padded row s (binary search over sp_off)
+  int lo = 0, hi = k;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (sp_off[mid] <= s) lo = mid; else hi = mid;
+  }
+  const int j = lo;
+  const bool real = s - sp_off[j] < cnt[j];
+  const float alpha = M == kCos ? 0.5f : 1.0f;
+  float row[C::KP];
+#pragma unroll
+  for (int c = 0; c < C::KP; ++c) row[c] = 0.f;
+  if (real) {
+    const float* y = Y32 + (size_t)s * DM;
+    const float* m = mu + (size_t)j * DM;
+    float ny = 0.f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) {
+      float v = y[c] - m[c];
+      if (P == 1) v = q_bf16(v);
+      ny = fmaf(v, v, ny);
+      row[c] = -2.0f * alpha * v;
+    }
+    const float bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
+    if (P == 0) {
+      row[DM] = 1.0f;
+      row[DM + 1] = bn;
+    } else {
+      row[DM] = row[DM + 1] = row[DM + 2] = 1.0f;
+      split3(bn, row[DM + 3], row[DM + 4], row[DM + 5]);
+    }
+  }
+  if (P == 0) {
+    float* out = (float*)Ym + (size_t)s * C::KP;
+#pragma unroll
+    for (int c = 0; c < C::KP; ++c) out[c] = row[c];
+  } else {
+    __bf16* out = (__bf16*)Ym + (size_t)s * C::KP;
+#pragma unroll
+    for (int c = 0; c < C::KP; ++c) out[c] = (__bf16)row[c];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 16 per-lane row sums, each over the lane's column: after the exchanges lane
+// l holds the sum over all 32 columns for row r = (l >> 1) & 15 of its half.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float transpose_reduce16(float (&v)[16], int lane) {
+  {
+    const bool up = lane & 16;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float send = up ? v[i] : v[i + 8];
+      const float keep = up ? v[i + 8] : v[i];
+      v[i] = keep + __shfl_xor(send, 16, kWave);
+    }
+  }
+  {
+    const bool up = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = up ? v[i] : v[i + 4];
+      const float keep = up ? v[i + 4] : v[i];
+      v[i] = keep + __shfl_xor(send, 8, kWave);
+    }
+  }
+  {
+    const bool up = lane & 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = up ? v[i] : v[i + 2];
+      const float keep = up ? v[i + 2] : v[i];
+      v[i] = keep + __shfl_xor(send, 4, kWave);
+    }
+  }
+  {
+    const bool up = lane & 2;
+    const float send = up ? v[0] : v[1];
+    const float keep = up ? v[1] : v[0];
+    v[0] = keep + __shfl_xor(send, 2, kWave);
+  }
+  return v[0] + __shfl_xor(v[0], 1, kWave);
+}
+
+template <int P, int DM>
+struct AFrag;
+template <int DM>
+struct AFrag<0, DM> {
+  float v[MCfg<0, DM>::NSTEP];
+};
+template <int DM>
+struct AFrag<1, DM> {
+  bf16x8 v[MCfg<1, DM>::NSTEP];
+};
+
+template <int M, int P, int DM>
+__global__ __launch_bounds__(256) void k_p2_mfma(
+    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+    const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ sp_off,
+    const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
+    const float* __restrict__ mu, float* __restrict__ a_out, float* __restrict__ b_out,
+    float* __restrict__ s_out, float* __restrict__ What, double* __restrict__ bpart) {
+  using C = MCfg<P, DM>;
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int col = lane & 31;
+  const int P0 = (blockIdx.x * 4 + wave) * 32;
+
+  // this lane's half of its A row (raw or unit-scaled), zero outside [0, d)
+  const int pa = P0 + col < n ? P0 + col : n - 1;
+  float xr[C::HALF];
+  {
+    const float* xp = X + (size_t)pa * d;
+#pragma unroll
+    for (int i = 0; i < C::HALF; ++i) {
+      const int c = h * C::HALF + i;
+      xr[i] = (c < DM && c < d) ? xp[c] : 0.0f;
+    }
+  }
+  float ux = 0.f;
+  if (M == kCos) {
+    float p = 0.f;
+#pragma unroll
+    for (int i = 0; i < C::HALF; ++i) p = fmaf(xr[i], xr[i], p);
+    const float s2 = p + __shfl_xor(p, 32, kWave);
+    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+    ux = s2 > 0.f ? 0.f : 0.5f;
+#pragma unroll
+    for (int i = 0; i < C::HALF; ++i) xr[i] *= rx;
+  }
+  const float alpha = M == kCos ? 0.5f : 1.0f;
+
+  // the element whose sums this lane ends up holding (twice: lanes l, l^1)
+  const int rr = (lane >> 1) & 15;
+  const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
+  const int pout = P0 + prow;
+  const bool pvalid = pout < n;
+  const int own = labels[pvalid ? pout : n - 1];
+
+  double w_own = 0.0;
+  double bmin = __builtin_inf();
+  AFrag<P, DM> A;
+
+  for (int j = 0; j < k; ++j) {
+    // ---- A operand for cluster j: x~ = x - mu_j, rounded, + augmentation
+    {
+      const float* m = mu + (size_t)j * DM;
+      float xq[C::HALF];
+      float part = 0.f;
+#pragma unroll
+      for (int i = 0; i < C::HALF; ++i) {
+        const int c = h * C::HALF + i;
+        float v = 0.f;
+        if (c < DM) {
+          v = xr[i] - m[c];
+          if (P == 1) v = q_bf16(v);
+          part = fmaf(v, v, part);
+        }
+        xq[i] = v;
+      }
+      const float nx = part + __shfl_xor(part, 32, kWave);
+      const float an = fmaf(alpha, nx, ux);
+      float aug[C::AUG];
+      if (P == 0) {
+        aug[0] = an;
+        aug[1] = 1.0f;
+      } else {
+        split3(an, aug[0], aug[1], aug[2]);
+        aug[3] = aug[4] = aug[5] = 1.0f;
+      }
+#pragma unroll
+      for (int i = 0; i < C::HALF; ++i) {
+        const int c = h * C::HALF + i;
+#pragma unroll
+        for (int q = 0; q < C::AUG; ++q)
+          if (c == DM + q) xq[i] = aug[q];
+      }
+      if constexpr (P == 0) {
+#pragma unroll
+        for (int s = 0; s < C::NSTEP; ++s) A.v[s] = xq[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < C::NSTEP; ++s)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) A.v[s][e] = (__bf16)xq[8 * s + e];
+      }
+    }
+
+    // ---- sweep the cluster's sample tiles
+    const int base = sp_off[j];
+    const int ntile = (cnt[j] + 31) >> 5;
+    double wsum = 0.0;
+    float acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    int g = 0;
+    for (int t = 0; t < ntile; ++t) {
+      const int srow = base + t * 32 + col;
+      const float wj = w[srow];
+      f32x16 c;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) c[r] = 0.f;
+      if constexpr (P == 0) {
+        const float2* bp = (const float2*)((const float*)Ym + (size_t)srow * C::KP + h * C::HALF);
+#pragma unroll
+        for (int s2 = 0; s2 < C::NSTEP / 2; ++s2) {
+          const float2 bv = bp[s2];
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2], bv.x, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2 + 1], bv.y, c, 0, 0, 0);
+        }
+      } else {
+        const bf16x8* bp = (const bf16x8*)((const __bf16*)Ym + (size_t)srow * C::KP + h * C::HALF);
+#pragma unroll
+        for (int s = 0; s < C::NSTEP; ++s) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v[s], bp[s], c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float dv;
+        if (M == kEucl)
+          dv = __builtin_amdgcn_sqrtf(fabsf(c[r]));
+        else
+          dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, 2.0f);
+        acc[r] = fmaf(wj, dv, acc[r]);
+      }
+      if (++g == kFold || t == ntile - 1) {
+        wsum += (double)transpose_reduce16(acc, lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+        g = 0;
+      }
+    }
+    if (What != nullptr && pvalid && (lane & 1) == 0) What[(size_t)pout * k + j] = (float)wsum;
+    const int sz = csize[j];
+    if (j == own) {
+      w_own = wsum;
+    } else if (sz > 0) {
+      const double bj = wsum / (double)sz;
+      bmin = bj < bmin ? bj : bmin;
+    }
+  }
+  const int szo = csize[own];
+  const double a = szo > 1 ? w_own / (double)(szo - 1) : 0.0;
+  const double b = bmin;
+  const double mx = a > b ? a : b;
+  const double s = (szo > 1 && mx > 0.0) ? (b - a) / mx : 0.0;
+  const bool writer = pvalid && (lane & 1) == 0;
+  if (writer) {
+    if (a_out) a_out[pout] = (float)a;
+    if (b_out) b_out[pout] = (float)b;
+    if (s_out) s_out[pout] = (float)s;
+  }
+  const double tot = block_sum_f64<256>(writer ? s : 0.0, sh);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
+}
+
+template <int M, int P, int DM>
+static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym) {
+  const int blocks = (int)ceil_div(A.n, 128);
+  hipLaunchKernelGGL((k_p2_mfma<M, P, DM>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
+                     A.w, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart);
+}
+
+template <int M, int P, int DM>
+static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, const int32_t* sp_off,
+                            const int32_t* cnt, int k, const float* mu, int S_pad, void* Ym) {
+  hipLaunchKernelGGL((k_pack_mfma<M, P, DM>), dim3((int)ceil_div(S_pad, 256)), dim3(256), 0, st, Y32,
+                     aux, sp_off, cnt, k, mu, S_pad, Ym);
+}
+
+#define SILH_MFMA_DISPATCH(FN, ...)                                     \
+  do {                                                                  \
+    if (metric == kEucl && prec == 0) {                                 \
+      switch (DM) {                                                     \
+        case 8: FN<kEucl, 0, 8>(__VA_ARGS__); return true;              \
+        case 16: FN<kEucl, 0, 16>(__VA_ARGS__); return true;            \
+        case 32: FN<kEucl, 0, 32>(__VA_ARGS__); return true;            \
+        case 64: FN<kEucl, 0, 64>(__VA_ARGS__); return true;            \
+        case 128: FN<kEucl, 0, 128>(__VA_ARGS__); return true;          \
+      }                                                                 \
+    } else if (metric == kEucl && prec == 1) {                          \
+      switch (DM) {                                                     \
+        case 8: FN<kEucl, 1, 8>(__VA_ARGS__); return true;              \
+        case 16: FN<kEucl, 1, 16>(__VA_ARGS__); return true;            \
+        case 32: FN<kEucl, 1, 32>(__VA_ARGS__); return true;            \
+        case 64: FN<kEucl, 1, 64>(__VA_ARGS__); return true;            \
+        case 128: FN<kEucl, 1, 128>(__VA_ARGS__); return true;          \
+      }                                                                 \
+    } else if (metric == kCos && prec == 0) {                           \
+      switch (DM) {                                                     \
+        case 8: FN<kCos, 0, 8>(__VA_ARGS__); return true;               \
+        case 16: FN<kCos, 0, 16>(__VA_ARGS__); return true;             \
+        case 32: FN<kCos, 0, 32>(__VA_ARGS__); return true;             \
+        case 64: FN<kCos, 0, 64>(__VA_ARGS__); return true;             \
+        case 128: FN<kCos, 0, 128>(__VA_ARGS__); return true;           \
+      }                                                                 \
+    } else if (metric == kCos && prec == 1) {                           \
+      switch (DM) {                                                     \
+        case 8: FN<kCos, 1, 8>(__VA_ARGS__); return true;               \
+        case 16: FN<kCos, 1, 16>(__VA_ARGS__); return true;             \
+        case 32: FN<kCos, 1, 32>(__VA_ARGS__); return true;             \
+        case 64: FN<kCos, 1, 64>(__VA_ARGS__); return true;             \
+        case 128: FN<kCos, 1, 128>(__VA_ARGS__); return true;           \
+      }                                                                 \
+    }                                                                   \
+    return false;                                                       \
+  } while (0)
+
+bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
+                      const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
+                      void* Ym) {
+  SILH_MFMA_DISPATCH(launch_pack_one, st, Y32, aux, sp_off, cnt, k, mu, S_pad, Ym);
+}
+
+bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
+                        const void* Ym) {
+  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym);
+}
+
+}  // namespace silh

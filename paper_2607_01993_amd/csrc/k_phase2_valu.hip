@@ -1,0 +1,203 @@
+// Phase 2 of Algorithm 1 on the vector ALUs (float32 distances; float64 sums
+// across tiles): for each element e and cluster C_j,
+//   W_hat_{C_j}(e) = sum_{e' in F_j} w_{e'} d(e, e'),  w = 1/p,
+// then a_hat, b_hat, s_hat (Eq. 5) and a per-block float64 partial of the sum
+// of s_hat (for Eq. 9).
+//
+// Mapping: one element per lane, its coordinates in registers; the whole wave
+// walks the packed sample in the same order, so every sample coordinate and
+// weight is wave-uniform and is read by scalar loads into SGPRs, which the
+// VALU instructions take as operands directly.  The loop over clusters is
+// uniform too, so the per-cluster running sums need no cross-lane traffic.
+#include <float.h>
+
+#include "device_common.hpp"
+#include "silh_internal.hpp"
+
+namespace silh {
+
+constexpr int kGroup = 32;  // samples summed in float32 before the float64 add
+
+template <int M, int DM>
+__device__ __forceinline__ float dist32(const float (&x)[DM], const float* __restrict__ y, float ux,
+                                      float uy) {
+  if (M == kEucl) {
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) {
+      const float df = x[c] - y[c];
+      s = fmaf(df, df, s);
+    }
+    return __builtin_amdgcn_sqrtf(s);
+  } else if (M == kManh) {
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) s += fabsf(x[c] - y[c]);
+    return s;
+  } else if (M == kCanb) {
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) {
+      const float den = fmaxf(fabsf(x[c]) + fabsf(y[c]), FLT_MIN);
+      s = fmaf(fabsf(x[c] - y[c]), __builtin_amdgcn_rcpf(den), s);
+    }
+    return s;
+  } else {
+    // cosine, as half the squared distance of the unit vectors plus u (0.5
+    // for a zero vector, else 0): for unit x_hat, y_hat,
+    // 1 - x_hat.y_hat = |x_hat - y_hat|^2 / 2, and the u terms give 1 whenever
+    // either vector is zero; this form does not cancel for near-parallel pairs.
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) {
+      const float df = x[c] - y[c];
+      s = fmaf(df, df, s);
+    }
+    return __builtin_amdgcn_fmed3f(fmaf(0.5f, s, ux + uy), 0.0f, 2.0f);
+  }
+}
+
+template <int M, int DM>
+__global__ __launch_bounds__(kP2Rows) void k_p2_valu(
+    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+    const float* __restrict__ Y, const float* __restrict__ w, const float* __restrict__ aux,
+    const int32_t* __restrict__ sp_off,
+    const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
+    float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
+    float* __restrict__ What, double* __restrict__ bpart) {
+  __shared__ double sh[kP2Rows / kWave];
+  const int e = blockIdx.x * kP2Rows + threadIdx.x;
+  const bool valid = e < n;
+  const int er = valid ? e : n - 1;
+
+  float x[DM];
+  const float* xr = X + (size_t)er * d;
+#pragma unroll
+  for (int c = 0; c < DM; ++c) x[c] = c < d ? xr[c] : 0.0f;
+  float ux = 0.f;
+  if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
+    float s2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) s2 = fmaf(x[c], x[c], s2);
+    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+    ux = s2 > 0.f ? 0.f : 0.5f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) x[c] *= rx;
+  }
+  const int own = labels[er];
+
+  double w_own = 0.0;
+  double bmin = __builtin_inf();
+  for (int j = 0; j < k; ++j) {
+    const int s0 = sp_off[j];
+    const int cj = cnt[j];
+    double accd = 0.0;
+    for (int g0 = 0; g0 < cj; g0 += kGroup) {
+      const int g1 = g0 + kGroup < cj ? g0 + kGroup : cj;
+      float acc = 0.f;
+      for (int q = g0; q < g1; ++q) {
+        const float* y = Y + (size_t)(s0 + q) * DM;
+        const float uy = M == kCos ? aux[s0 + q] : 0.f;
+        acc = fmaf(w[s0 + q], dist32<M, DM>(x, y, ux, uy), acc);
+      }
+      accd += (double)acc;
+    }
+    if (What != nullptr && valid) What[(size_t)e * k + j] = (float)accd;
+    const int sz = csize[j];
+    if (j == own) {
+      w_own = accd;
+    } else if (sz > 0) {
+      const double bj = accd / (double)sz;
+      bmin = bj < bmin ? bj : bmin;
+    }
+  }
+  const int szo = csize[own];
+  const double a = szo > 1 ? w_own / (double)(szo - 1) : 0.0;
+  const double b = bmin;
+  const double mx = a > b ? a : b;
+  const double s = (szo > 1 && mx > 0.0) ? (b - a) / mx : 0.0;
+  if (valid) {
+    if (a_out) a_out[e] = (float)a;
+    if (b_out) b_out[e] = (float)b;
+    if (s_out) s_out[e] = (float)s;
+  }
+  const double tot = block_sum_f64<kP2Rows>(valid ? s : 0.0, sh);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
+}
+
+int phase2_valu_dm(int d) {
+  if (d <= 8) return 8;
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  if (d <= 128) return 128;
+  return 0;
+}
+
+template <int M, int DM>
+static void launch_one(hipStream_t st, const P2Args& A) {
+  const int blocks = (int)ceil_div(A.n, kP2Rows);
+  hipLaunchKernelGGL((k_p2_valu<M, DM>), dim3(blocks), dim3(kP2Rows), 0, st, A.X, A.n, A.d, A.labels,
+                     A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What, A.bpart);
+}
+
+template <int M>
+static bool launch_metric(hipStream_t st, int DM, const P2Args& A) {
+  switch (DM) {
+    case 8: launch_one<M, 8>(st, A); return true;
+    case 16: launch_one<M, 16>(st, A); return true;
+    case 32: launch_one<M, 32>(st, A); return true;
+    case 64: launch_one<M, 64>(st, A); return true;
+    case 128: launch_one<M, 128>(st, A); return true;
+    default: return false;
+  }
+}
+
+bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& A) {
+  switch (metric) {
+    case kEucl: return launch_metric<kEucl>(st, DM, A);
+    case kCos: return launch_metric<kCos>(st, DM, A);
+    case kManh: return launch_metric<kManh>(st, DM, A);
+    case kCanb: return launch_metric<kCanb>(st, DM, A);
+    default: return false;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Eq. 9: (1/n) * sum of the per-block partials, float64 with Neumaier
+// compensation, fixed order (thread-strided, then a tree over threads).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
+  const double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+__global__ __launch_bounds__(256) void k_mean(const double* __restrict__ bpart, int nb, int64_t n,
+                                              double* __restrict__ out) {
+  __shared__ double ss[256], cc[256];
+  double s = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) neumaier_add(s, c, bpart[i]);
+  ss[threadIdx.x] = s;
+  cc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      double s1 = ss[threadIdx.x], c1 = cc[threadIdx.x] + cc[threadIdx.x + o];
+      neumaier_add(s1, c1, ss[threadIdx.x + o]);
+      ss[threadIdx.x] = s1;
+      cc[threadIdx.x] = c1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (ss[0] + cc[0]) / (double)n;
+}
+
+void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, bpart, nb, n, out);
+}
+
+}  // namespace silh

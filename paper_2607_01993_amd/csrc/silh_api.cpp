@@ -1,0 +1,686 @@
+// C ABI of the silhouette library: argument checks, the per-clustering
+// context, the call order, device-memory management through the caller's
+// allocator, and the order of kernel launches on the caller's stream.
+#include "../../include/silh.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "silh_internal.hpp"
+
+using namespace silh;
+
+namespace {
+
+thread_local std::string g_err;
+
+silh_status fail(silh_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(SILH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(expr)                      \
+  do {                                 \
+    silh_status s_ = (expr);           \
+    if (s_ != SILH_OK) return s_;      \
+  } while (0)
+
+enum Slot {
+  K_COUNT = 0,
+  K_SORT_HIST,
+  K_SORT_SCAN,
+  K_SORT_SCATTER,
+  K_F0_FLAG,
+  K_SCAN,
+  K_F0_PACK,
+  K_W_PARTIAL,
+  K_W_FINAL,
+  K_DRAW,
+  K_PACK,
+  K_CENTER,
+  K_PACK_MFMA,
+  K_PHASE2,
+  K_MEAN,
+  K_NSLOTS
+};
+const char* const kSlotNames[K_NSLOTS] = {
+    "count",   "sort_hist", "sort_scan", "sort_scatter", "f0_flag", "scan", "f0_pack",
+    "w_partial", "w_final", "draw",      "pack",         "center",  "pack_mfma", "phase2", "mean"};
+
+constexpr int64_t kMaxN = (int64_t)1 << 30;
+constexpr int kMaxK = 4096;
+constexpr int kMaxD = 256;
+
+}  // namespace
+
+struct silh_ctx {
+  silh_params prm{};
+  int64_t t = 0;
+  hipStream_t st = nullptr;
+  const float* X = nullptr;
+  const int32_t* labels = nullptr;
+  int n = 0, d = 0, k = 0, DM = 0;
+  bool mfma = false;  // Phase 2 on the matrix cores
+  int p2_rows = kP2Rows;
+  int state = 0;  // 0 = indexed, 1 = sampled
+
+  std::vector<void*> alloc_init, alloc_sample;
+
+  // host copies
+  std::vector<uint32_t> counts_h;
+  std::vector<int32_t> csize_h, off_h;
+  std::vector<double> q_h;
+  std::vector<int32_t> f0_off32_h, s_off32_h, sp_off_h, cnt_h, items_h, citem_first_h, citem_count_h;
+  std::vector<int64_t> f0_off_h, s_off_h;
+  int bad_h = 0;
+  double mean_h = 0.0;
+
+  // index
+  int32_t* csize = nullptr;  // u32 counts reinterpreted (sizes < 2^31)
+  int* bad = nullptr;
+  int32_t* off = nullptr;
+  int32_t* uh = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* slab = nullptr;
+  double* q = nullptr;
+
+  // sample
+  int64_t S = 0, S_pad = 0, F0 = 0;
+  int32_t *flag = nullptr, *pos = nullptr, *scan_tmp = nullptr;
+  int32_t *f0_off = nullptr, *f0_cl = nullptr, *items = nullptr, *citem_first = nullptr,
+          *citem_count = nullptr;
+  int64_t *f0_gid = nullptr, *gid_view = nullptr;
+  double *f0X = nullptr, *W0 = nullptr, *partial = nullptr, *p_gid = nullptr;
+  int32_t *s_off = nullptr, *sp_off = nullptr, *cnt = nullptr, *gid_pk = nullptr;
+  float *w32 = nullptr, *aux32 = nullptr, *Y32 = nullptr, *mu = nullptr;
+  void* Ym = nullptr;
+  double *bpart = nullptr, *mean_d = nullptr;
+
+  // profiling
+  bool prof_on = false;
+  struct Pending {
+    int slot;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double tot_ms[K_NSLOTS] = {};
+  int64_t launches[K_NSLOTS] = {};
+};
+
+namespace {
+
+void* raw_alloc(silh_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (c->prm.alloc) return c->prm.alloc(bytes, c->prm.alloc_user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void raw_free(silh_ctx* c, void* p) {
+  if (!p) return;
+  if (c->prm.alloc) {
+    if (c->prm.free) c->prm.free(p, c->prm.alloc_user);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+template <class T>
+silh_status dalloc(silh_ctx* c, std::vector<void*>& list, T** out, size_t count) {
+  void* p = raw_alloc(c, count * sizeof(T));
+  if (!p) return fail(SILH_E_NOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+  list.push_back(p);
+  *out = (T*)p;
+  return SILH_OK;
+}
+
+void free_list(silh_ctx* c, std::vector<void*>& list) {
+  for (void* p : list) raw_free(c, p);
+  list.clear();
+}
+
+hipEvent_t get_event(silh_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets a kernel launch with events when profiling is on, and checks the
+// launch status afterwards.
+struct Launch {
+  silh_ctx* c;
+  int slot;
+  hipEvent_t a = nullptr;
+  Launch(silh_ctx* ctx, int s) : c(ctx), slot(s) {
+    if (c->prof_on) {
+      a = get_event(c);
+      if (a) (void)hipEventRecord(a, c->st);
+    }
+  }
+  silh_status done() {
+    hipError_t e = hipGetLastError();
+    if (c->prof_on && a) {
+      hipEvent_t b = get_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->st);
+        c->pending.push_back({slot, a, b});
+      } else {
+        c->pool.push_back(a);
+      }
+      a = nullptr;
+    }
+    if (e != hipSuccess) return fail(SILH_E_HIP, "kernel %s: %s", kSlotNames[slot], hipGetErrorString(e));
+    return SILH_OK;
+  }
+};
+
+silh_status drain_prof(silh_ctx* c) {
+  if (c->pending.empty()) return SILH_OK;
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->tot_ms[p.slot] += ms;
+      c->launches[p.slot] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return SILH_OK;
+}
+
+template <class T>
+silh_status h2d(silh_ctx* c, T* dst, const std::vector<T>& src) {
+  if (src.empty()) return SILH_OK;
+  HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->st));
+  return SILH_OK;
+}
+
+silh_status check_params(const silh_params* prm, const float* X, const int32_t* labels, bool exact,
+                         int64_t* t_out) {
+  if (!prm) return fail(SILH_E_ARG, "params is NULL");
+  if (!X || !labels) return fail(SILH_E_ARG, "X or labels is NULL");
+  if (prm->n < 2 || prm->n > kMaxN) return fail(SILH_E_ARG, "n=%lld outside [2, 2^30]", (long long)prm->n);
+  if (prm->d < 1 || prm->d > kMaxD) return fail(SILH_E_ARG, "d=%d outside [1, %d]", prm->d, kMaxD);
+  if (prm->k < 2 || prm->k > kMaxK) return fail(SILH_E_ARG, "k=%d outside [2, %d]", prm->k, kMaxK);
+  if (prm->metric < 0 || prm->metric > 3) return fail(SILH_E_ARG, "unknown metric %d", prm->metric);
+  if (prm->prec < 0 || prm->prec > 3) return fail(SILH_E_ARG, "unknown precision %d", prm->prec);
+  if (prm->reserved0 != 0) return fail(SILH_E_ARG, "reserved0 must be 0");
+  if ((prm->alloc == nullptr) != (prm->free == nullptr))
+    return fail(SILH_E_ARG, "alloc and free must be given together");
+  const bool mfma_metric = prm->metric == SILH_EUCL || prm->metric == SILH_COS;
+  if (prm->prec == SILH_FP8 || (prm->prec == SILH_BF16 && !mfma_metric))
+    return fail(SILH_E_UNSUPPORTED, "precision %d is not built for metric %d", prm->prec, prm->metric);
+  if (phase2_valu_dm(prm->d) == 0)
+    return fail(SILH_E_UNSUPPORTED, "d=%d has no Phase-2 kernel (d <= 128)", prm->d);
+  int64_t t = prm->t;
+  if (!exact) {
+    if (prm->sampler < 0 || prm->sampler > 1) return fail(SILH_E_ARG, "unknown sampler %d", prm->sampler);
+    if (!(prm->delta > 0.0 && prm->delta < 1.0)) return fail(SILH_E_ARG, "delta must be in (0, 1)");
+    if (t <= 0) {
+      if (!(prm->eps > 0.0 && prm->eps < 1.0))
+        return fail(SILH_E_ARG, "t <= 0 needs eps in (0, 1)");
+      // Lemma 1: t = ceil((3c/eps^2) ln(5nk/delta)), c = 18
+      const double v = std::ceil((3.0 * 18.0 / (prm->eps * prm->eps)) *
+                                 std::log(5.0 * (double)prm->n * (double)prm->k / prm->delta));
+      if (!(v < 9.0e18)) return fail(SILH_E_ARG, "derived t overflows");
+      t = (int64_t)v;
+    }
+  }
+  *t_out = t;
+  return SILH_OK;
+}
+
+// Cluster sizes, offsets and the stable sort by label.
+silh_status build_index(silh_ctx* c) {
+  const int n = c->n, k = c->k;
+  CHK(dalloc(c, c->alloc_init, &c->csize, (size_t)k));
+  CHK(dalloc(c, c->alloc_init, &c->bad, 1));
+  HIPCHK(hipMemsetAsync(c->csize, 0, (size_t)k * sizeof(int32_t), c->st));
+  HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
+  {
+    Launch L(c, K_COUNT);
+    launch_count(c->st, c->labels, n, k, (uint32_t*)c->csize, c->bad);
+    CHK(L.done());
+  }
+  c->counts_h.assign(k, 0u);
+  HIPCHK(hipMemcpyAsync(c->counts_h.data(), c->csize, k * sizeof(uint32_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(&c->bad_h, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (c->bad_h) return fail(SILH_E_LABEL, "a label lies outside [0, %d)", k);
+  c->csize_h.assign(k, 0);
+  c->off_h.assign(k + 1, 0);
+  int nonempty = 0;
+  for (int j = 0; j < k; ++j) {
+    c->csize_h[j] = (int32_t)c->counts_h[j];
+    c->off_h[j + 1] = c->off_h[j] + c->csize_h[j];
+    nonempty += c->csize_h[j] > 0;
+  }
+  if (nonempty < 2) return fail(SILH_E_K, "%d nonempty cluster(s); the silhouette needs at least 2", nonempty);
+  // initial-sample rate of Algorithm 1, min(1, (2/|C_j|) ln(5k/delta)), on the host
+  c->q_h.assign(k, 0.0);
+  const double lnterm = std::log(5.0 * (double)k / c->prm.delta);
+  for (int j = 0; j < k; ++j) {
+    if (c->csize_h[j] > 0) {
+      double qj = 2.0 / (double)c->csize_h[j];
+      qj = qj * lnterm;
+      c->q_h[j] = qj < 1.0 ? qj : 1.0;
+    }
+  }
+  CHK(dalloc(c, c->alloc_init, &c->off, (size_t)k + 1));
+  CHK(dalloc(c, c->alloc_init, &c->q, (size_t)k));
+  CHK(h2d(c, c->off, c->off_h));
+  CHK(h2d(c, c->q, c->q_h));
+  const int units = (int)ceil_div(n, kSortSeg);
+  CHK(dalloc(c, c->alloc_init, &c->uh, (size_t)units * k));
+  CHK(dalloc(c, c->alloc_init, &c->perm, (size_t)n));
+  CHK(dalloc(c, c->alloc_init, &c->slab, (size_t)n));
+  {
+    Launch L(c, K_SORT_HIST);
+    launch_unit_hist(c->st, c->labels, n, k, c->uh);
+    CHK(L.done());
+  }
+  {
+    Launch L(c, K_SORT_SCAN);
+    launch_unit_scan(c->st, c->uh, units, k, c->off);
+    CHK(L.done());
+  }
+  {
+    Launch L(c, K_SORT_SCATTER);
+    launch_scatter(c->st, c->labels, n, k, c->uh, c->perm, c->slab);
+    CHK(L.done());
+  }
+  return SILH_OK;
+}
+
+silh_status create(const silh_params* prm, const float* X, const int32_t* labels, silh_stream stream,
+                   bool exact, silh_ctx** out) {
+  int64_t t = 0;
+  CHK(check_params(prm, X, labels, exact, &t));
+  silh_ctx* c = new (std::nothrow) silh_ctx();
+  if (!c) return fail(SILH_E_NOMEM, "host allocation failed");
+  c->prm = *prm;
+  c->t = t;
+  c->st = (hipStream_t)stream;
+  c->X = X;
+  c->labels = labels;
+  c->n = (int)prm->n;
+  c->d = prm->d;
+  c->k = prm->k;
+  c->DM = phase2_valu_dm(prm->d);
+  c->mfma = (prm->metric == SILH_EUCL || prm->metric == SILH_COS) &&
+            (prm->prec == SILH_FP32 || prm->prec == SILH_BF16);
+  c->p2_rows = c->mfma ? 128 : kP2Rows;
+  silh_status s = build_index(c);
+  if (s != SILH_OK) {
+    std::string msg = g_err;
+    silh_destroy(c);
+    g_err = msg;
+    return s;
+  }
+  *out = c;
+  return SILH_OK;
+}
+
+// Scan the selection flags, read the per-cluster sample counts back, and pack
+// the selected rows into the padded cluster-blocked layout.
+silh_status compact_and_pack(silh_ctx* c) {
+  const int n = c->n, k = c->k;
+  {
+    Launch L(c, K_SCAN);
+    launch_scan(c->st, c->flag, n, c->pos, c->scan_tmp);
+    CHK(L.done());
+  }
+  CHK(dalloc(c, c->alloc_sample, &c->s_off, (size_t)k + 1));
+  launch_gather_at(c->st, c->pos, c->off, k, c->s_off);
+  HIPCHK(hipGetLastError());
+  c->s_off32_h.assign(k + 1, 0);
+  HIPCHK(hipMemcpyAsync(c->s_off32_h.data(), c->s_off, (k + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  c->s_off_h.assign(k + 1, 0);
+  c->cnt_h.assign(k, 0);
+  c->sp_off_h.assign(k + 1, 0);
+  for (int j = 0; j <= k; ++j) c->s_off_h[j] = c->s_off32_h[j];
+  for (int j = 0; j < k; ++j) {
+    c->cnt_h[j] = c->s_off32_h[j + 1] - c->s_off32_h[j];
+    c->sp_off_h[j + 1] = c->sp_off_h[j] + (int32_t)(ceil_div(c->cnt_h[j], kSamplePad) * kSamplePad);
+  }
+  c->S = c->s_off_h[k];
+  c->S_pad = c->sp_off_h[k];
+  CHK(dalloc(c, c->alloc_sample, &c->sp_off, (size_t)k + 1));
+  CHK(dalloc(c, c->alloc_sample, &c->cnt, (size_t)k));
+  CHK(h2d(c, c->sp_off, c->sp_off_h));
+  CHK(h2d(c, c->cnt, c->cnt_h));
+  CHK(dalloc(c, c->alloc_sample, &c->gid_view, (size_t)c->S));
+  CHK(dalloc(c, c->alloc_sample, &c->gid_pk, (size_t)c->S_pad));
+  CHK(dalloc(c, c->alloc_sample, &c->w32, (size_t)c->S_pad));
+  CHK(dalloc(c, c->alloc_sample, &c->aux32, (size_t)c->S_pad));
+  CHK(dalloc(c, c->alloc_sample, &c->Y32, (size_t)c->S_pad * c->DM));
+  HIPCHK(hipMemsetAsync(c->gid_pk, 0xFF, (size_t)c->S_pad * sizeof(int32_t), c->st));
+  HIPCHK(hipMemsetAsync(c->w32, 0, (size_t)c->S_pad * sizeof(float), c->st));
+  HIPCHK(hipMemsetAsync(c->aux32, 0, (size_t)c->S_pad * sizeof(float), c->st));
+  HIPCHK(hipMemsetAsync(c->Y32, 0, (size_t)c->S_pad * c->DM * sizeof(float), c->st));
+  {
+    Launch L(c, K_PACK);
+    launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, c->d, c->DM, c->p_gid, c->s_off,
+                c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, c->gid_view, c->gid_pk, c->w32, c->aux32,
+                c->Y32);
+    CHK(L.done());
+  }
+  if (c->mfma && c->S_pad > 0) {
+    const int prec = c->prm.prec == SILH_BF16 ? 1 : 0;
+    const int KP = mfma_kp(prec, c->DM);
+    CHK(dalloc(c, c->alloc_sample, &c->mu, (size_t)k * c->DM));
+    void* ym = raw_alloc(c, (size_t)c->S_pad * KP * (prec ? 2 : 4));
+    if (!ym) return fail(SILH_E_NOMEM, "device allocation of the packed sample failed");
+    c->alloc_sample.push_back(ym);
+    c->Ym = ym;
+    {
+      Launch L(c, K_CENTER);
+      launch_center(c->st, c->Y32, c->DM, c->sp_off, c->cnt, k, c->mu);
+      CHK(L.done());
+    }
+    {
+      Launch L(c, K_PACK_MFMA);
+      if (!launch_pack_mfma(c->st, c->prm.metric, prec, c->DM, c->Y32, c->aux32, c->sp_off, c->cnt, k,
+                            c->mu, (int)c->S_pad, c->Ym))
+        return fail(SILH_E_UNSUPPORTED, "no MFMA packing for metric %d, d=%d", c->prm.metric, c->d);
+      CHK(L.done());
+    }
+  }
+  const int nb = (int)ceil_div(n, c->p2_rows);
+  CHK(dalloc(c, c->alloc_sample, &c->bpart, (size_t)nb));
+  CHK(dalloc(c, c->alloc_sample, &c->mean_d, 1));
+  c->state = 1;
+  return SILH_OK;
+}
+
+silh_status sample_stage_buffers(silh_ctx* c) {
+  free_list(c, c->alloc_sample);
+  c->state = 0;
+  const int n = c->n;
+  CHK(dalloc(c, c->alloc_sample, &c->flag, (size_t)n));
+  CHK(dalloc(c, c->alloc_sample, &c->pos, (size_t)n + 1));
+  CHK(dalloc(c, c->alloc_sample, &c->scan_tmp, (size_t)ceil_div(n, kScanTile) + 1));
+  CHK(dalloc(c, c->alloc_sample, &c->p_gid, (size_t)n));
+  return SILH_OK;
+}
+
+silh_status phase1(silh_ctx* c) {
+  const int n = c->n, k = c->k, d = c->d;
+  CHK(sample_stage_buffers(c));
+  CHK(dalloc(c, c->alloc_sample, &c->f0_off, (size_t)k + 1));
+  c->F0 = 0;
+  c->f0_off_h.assign(k + 1, 0);
+  c->f0_off32_h.assign(k + 1, 0);
+  const bool pps = c->prm.sampler == SILH_PPS;
+  if (pps) {
+    // initial sample F^0
+    {
+      Launch L(c, K_F0_FLAG);
+      launch_f0_flag(c->st, c->perm, c->slab, n, c->csize, c->q, c->t, c->prm.seed, c->flag);
+      CHK(L.done());
+    }
+    {
+      Launch L(c, K_SCAN);
+      launch_scan(c->st, c->flag, n, c->pos, c->scan_tmp);
+      CHK(L.done());
+    }
+    launch_gather_at(c->st, c->pos, c->off, k, c->f0_off);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->f0_off32_h.data(), c->f0_off, (k + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int j = 0; j <= k; ++j) c->f0_off_h[j] = c->f0_off32_h[j];
+    c->F0 = c->f0_off_h[k];
+  } else {
+    HIPCHK(hipMemsetAsync(c->f0_off, 0, (size_t)(k + 1) * sizeof(int32_t), c->st));
+  }
+  CHK(dalloc(c, c->alloc_sample, &c->f0_gid, (size_t)c->F0));
+  CHK(dalloc(c, c->alloc_sample, &c->f0_cl, (size_t)c->F0));
+  CHK(dalloc(c, c->alloc_sample, &c->f0X, (size_t)c->F0 * d));
+  CHK(dalloc(c, c->alloc_sample, &c->W0, (size_t)c->F0));
+  if (pps && c->F0 > 0) {
+    {
+      Launch L(c, K_F0_PACK);
+      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->f0_gid, c->f0_cl, c->f0X);
+      CHK(L.done());
+    }
+    // work items for W(e_bar)
+    c->items_h.clear();
+    c->citem_first_h.assign(k, 0);
+    c->citem_count_h.assign(k, 0);
+    int64_t pbase = 0;
+    for (int j = 0; j < k; ++j) {
+      const int fj = c->f0_off32_h[j + 1] - c->f0_off32_h[j];
+      c->citem_first_h[j] = (int32_t)(c->items_h.size() / 6);
+      if ((int64_t)c->csize_h[j] <= c->t || fj == 0) continue;
+      for (int b = c->off_h[j]; b < c->off_h[j + 1]; b += kWChunk) {
+        const int e = b + kWChunk < c->off_h[j + 1] ? b + kWChunk : c->off_h[j + 1];
+        c->items_h.insert(c->items_h.end(), {j, b, e, c->f0_off32_h[j], fj, (int32_t)pbase});
+        pbase += fj;
+        c->citem_count_h[j] += 1;
+      }
+      if (pbase > (int64_t)1 << 30) return fail(SILH_E_ARG, "initial sample too large");
+    }
+    const int nitems = (int)(c->items_h.size() / 6);
+    CHK(dalloc(c, c->alloc_sample, &c->items, c->items_h.size()));
+    CHK(dalloc(c, c->alloc_sample, &c->citem_first, (size_t)k));
+    CHK(dalloc(c, c->alloc_sample, &c->citem_count, (size_t)k));
+    CHK(dalloc(c, c->alloc_sample, &c->partial, (size_t)pbase));
+    CHK(h2d(c, c->items, c->items_h));
+    CHK(h2d(c, c->citem_first, c->citem_first_h));
+    CHK(h2d(c, c->citem_count, c->citem_count_h));
+    {
+      Launch L(c, K_W_PARTIAL);
+      launch_w_partial(c->st, c->prm.metric, c->items, nitems, c->perm, c->X, d, c->f0X, c->partial);
+      CHK(L.done());
+    }
+    {
+      Launch L(c, K_W_FINAL);
+      launch_w_final(c->st, c->f0_cl, (int)c->F0, c->f0_off, c->citem_first, c->citem_count, c->items,
+                     c->partial, c->W0);
+      CHK(L.done());
+    }
+  }
+  {
+    Launch L(c, K_DRAW);
+    launch_draw(c->st, c->prm.metric, pps ? 0 : 1, c->perm, c->slab, n, c->X, d, c->csize, c->t,
+                c->prm.seed, c->f0_off, c->f0X, c->W0, c->p_gid, c->flag);
+    CHK(L.done());
+  }
+  return compact_and_pack(c);
+}
+
+silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, double* mean_host) {
+  P2Args A;
+  A.X = c->X;
+  A.n = c->n;
+  A.d = c->d;
+  A.labels = c->labels;
+  A.Y = c->Y32;
+  A.w = c->w32;
+  A.aux = c->aux32;
+  A.sp_off = c->sp_off;
+  A.cnt = c->cnt;
+  A.csize = c->csize;
+  A.k = c->k;
+  A.a = a;
+  A.b = b;
+  A.s = s;
+  A.What = What;
+  A.bpart = c->bpart;
+  {
+    Launch L(c, K_PHASE2);
+    const bool ok = c->mfma ? launch_phase2_mfma(c->st, c->prm.metric, c->prm.prec == SILH_BF16 ? 1 : 0,
+                                                 c->DM, A, c->mu, c->Ym)
+                            : launch_phase2_valu(c->st, c->prm.metric, c->DM, A);
+    if (!ok) return fail(SILH_E_UNSUPPORTED, "no Phase-2 kernel for metric %d, d=%d", c->prm.metric, c->d);
+    CHK(L.done());
+  }
+  if (mean_host) {
+    {
+      Launch L(c, K_MEAN);
+      launch_mean(c->st, c->bpart, (int)ceil_div(c->n, c->p2_rows), c->n, c->mean_d);
+      CHK(L.done());
+    }
+    HIPCHK(hipMemcpyAsync(&c->mean_h, c->mean_d, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    *mean_host = c->mean_h;
+  }
+  return SILH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+silh_status silh_sample_init(const silh_params* prm, const float* X, const int32_t* labels,
+                             silh_stream stream, silh_ctx** out) {
+  if (!out) return fail(SILH_E_ARG, "out is NULL");
+  *out = nullptr;
+  return create(prm, X, labels, stream, false, out);
+}
+
+silh_status silh_pps_sample(silh_ctx* c, int64_t* S_host, int64_t* per_cluster_host) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  silh_status s = phase1(c);
+  if (s != SILH_OK) {
+    c->state = 0;
+    return s;
+  }
+  if (S_host) *S_host = c->S;
+  if (per_cluster_host)
+    for (int j = 0; j < c->k; ++j) per_cluster_host[j] = c->cnt_h[j];
+  return SILH_OK;
+}
+
+silh_status silh_weighted_sums(silh_ctx* c, float* W_hat) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  if (!W_hat) return fail(SILH_E_ARG, "W_hat is NULL");
+  if (c->state != 1) return fail(SILH_E_STATE, "silh_weighted_sums before a successful silh_pps_sample");
+  return run_phase2(c, nullptr, nullptr, nullptr, W_hat, nullptr);
+}
+
+silh_status silh_scores(silh_ctx* c, float* a, float* b, float* s, double* s_mean_host) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  if (c->state != 1) return fail(SILH_E_STATE, "silh_scores before a successful silh_pps_sample");
+  return run_phase2(c, a, b, s, nullptr, s_mean_host);
+}
+
+silh_status silh_exact(const silh_params* prm, const float* X, const int32_t* labels, silh_stream stream,
+                       float* a, float* b, float* s, double* s_mean_host) {
+  silh_ctx* c = nullptr;
+  CHK(create(prm, X, labels, stream, true, &c));
+  silh_status st = sample_stage_buffers(c);
+  if (st == SILH_OK) {
+    Launch L(c, K_DRAW);
+    launch_fill_all(c->st, c->perm, c->n, c->p_gid, c->flag);
+    st = L.done();
+  }
+  if (st == SILH_OK) st = compact_and_pack(c);
+  if (st == SILH_OK) st = run_phase2(c, a, b, s, nullptr, s_mean_host);
+  std::string msg = g_err;
+  silh_destroy(c);
+  g_err = msg;
+  return st;
+}
+
+silh_status silh_sample_view(silh_ctx* c, silh_sample_info* out) {
+  if (!c || !out) return fail(SILH_E_ARG, "ctx or out is NULL");
+  if (c->state != 1) return fail(SILH_E_STATE, "silh_sample_view before a successful silh_pps_sample");
+  out->S = c->S;
+  out->gid = c->gid_view;
+  out->offsets_host = c->s_off_h.data();
+  out->p = c->p_gid;
+  out->F0 = c->F0;
+  out->f0_gid = c->f0_gid;
+  out->f0_W = c->W0;
+  out->f0_offsets_host = c->f0_off_h.data();
+  out->t = c->t;
+  return SILH_OK;
+}
+
+silh_status silh_philox_uniform(uint64_t seed, int64_t gid0, int64_t count, uint32_t stream_id,
+                                double* out, silh_stream stream) {
+  if (count < 0 || gid0 < 0) return fail(SILH_E_ARG, "count and gid0 must be >= 0");
+  if (count > 0 && !out) return fail(SILH_E_ARG, "out is NULL");
+  launch_uniform((hipStream_t)stream, seed, gid0, count, stream_id, out);
+  HIPCHK(hipGetLastError());
+  return SILH_OK;
+}
+
+silh_status silh_prof_enable(silh_ctx* c, int on) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  c->prof_on = on != 0;
+  return SILH_OK;
+}
+
+silh_status silh_prof_reset(silh_ctx* c) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  CHK(drain_prof(c));
+  for (int i = 0; i < K_NSLOTS; ++i) {
+    c->tot_ms[i] = 0.0;
+    c->launches[i] = 0;
+  }
+  return SILH_OK;
+}
+
+int silh_prof_count(void) { return K_NSLOTS; }
+
+silh_status silh_prof_get(silh_ctx* c, int i, const char** name, int64_t* launches, double* total_ms) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  if (i < 0 || i >= K_NSLOTS) return fail(SILH_E_ARG, "slot %d outside [0, %d)", i, (int)K_NSLOTS);
+  CHK(drain_prof(c));
+  if (name) *name = kSlotNames[i];
+  if (launches) *launches = c->launches[i];
+  if (total_ms) *total_ms = c->tot_ms[i];
+  return SILH_OK;
+}
+
+void silh_destroy(silh_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  for (auto& p : c->pending) {
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  free_list(c, c->alloc_sample);
+  free_list(c, c->alloc_init);
+  delete c;
+}
+
+const char* silh_last_error(void) { return g_err.c_str(); }
+
+const char* silh_version(void) { return "silh-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

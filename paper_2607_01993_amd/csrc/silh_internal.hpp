@@ -1,0 +1,99 @@
+// Internal interface between the C ABI (silh_api.cpp) and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace silh {
+
+// Rows per unit of the stable counting sort (one wave per unit).
+constexpr int kSortSeg = 1024;
+// Elements per block of the int32 exclusive scan (256 threads x 8).
+constexpr int kScanTile = 2048;
+// Members per work item of the W(e_bar) partial sums.
+constexpr int kWChunk = 2048;
+// Sample rows of each cluster are padded to a multiple of this.
+constexpr int kSamplePad = 32;
+// Rows per Phase-2 block in the VALU kernel.
+constexpr int kP2Rows = 256;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---- cluster index -------------------------------------------------------
+void launch_count(hipStream_t st, const int32_t* labels, int n, int k, uint32_t* counts, int* bad);
+void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh);
+void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, const int32_t* off);
+void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, const int32_t* ubase,
+                    int32_t* perm, int32_t* slab);
+// out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.  tmp holds
+// ceil_div(n, kScanTile) + 1 ints.
+void launch_scan(hipStream_t st, const int32_t* in, int n, int32_t* out, int32_t* tmp);
+// out[j] = scan[off[j]] for j in [0, k]
+void launch_gather_at(hipStream_t st, const int32_t* scan, const int32_t* off, int k, int32_t* out);
+
+// ---- Phase 1 -----------------------------------------------------------------
+void launch_f0_flag(hipStream_t st, const int32_t* perm, const int32_t* slab, int n,
+                    const int32_t* csize, const double* q, int64_t t, uint64_t seed, int32_t* flag);
+void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
+                    const int32_t* pos, int n, const float* X, int d, int64_t* f0_gid,
+                    int32_t* f0_cl, double* f0X);
+// one block per work item: item = (cluster, first sorted pos, end sorted pos,
+// first F0 index of the cluster, |F0_j|, base in `partial`)
+void launch_w_partial(hipStream_t st, int metric, const int32_t* items, int nitems,
+                      const int32_t* perm, const float* X, int d, const double* f0X, double* partial);
+void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off,
+                    const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
+                    const double* partial, double* W);
+void launch_draw(hipStream_t st, int metric, int sampler, const int32_t* perm, const int32_t* slab,
+                 int n, const float* X, int d, const int32_t* csize, int64_t t, uint64_t seed,
+                 const int32_t* f0_off, const double* f0X, const double* W, double* p_gid,
+                 int32_t* flag);
+void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, int32_t* flag);
+// Scatter the selected elements into the cluster-blocked, padded sample.
+// mode 0: raw coordinates; 1: rows scaled to unit L2 norm (cosine).
+void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
+                 const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
+                 const int32_t* s_off, const int32_t* sp_off, int mode, int64_t* gid_view,
+                 int32_t* gid_pk, float* w32, float* aux32, float* Y32);
+
+// ---- Phase 2 -----------------------------------------------------------------
+struct P2Args {
+  const float* X;
+  int n, d;
+  const int32_t* labels;
+  const float* Y;      // [S_pad][DM]
+  const float* w;      // [S_pad]
+  const float* aux;    // [S_pad] cosine: 0.5 for a zero sample vector, else 0
+  const int32_t* sp_off;  // [k+1] padded sample offsets
+  const int32_t* cnt;     // [k] |F_j|
+  const int32_t* csize;   // [k] |C_j|
+  int k;
+  float* a;
+  float* b;
+  float* s;
+  float* What;          // [n][k] or null
+  double* bpart;        // [ceil(n / kP2Rows)]
+};
+// returns false if (metric, d) has no VALU kernel
+bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& a);
+int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if unsupported
+
+// MFMA path (Euclidean, cosine; float32 or bf16 operands)
+int mfma_kp(int prec, int DM);   // contraction length of a packed row
+void launch_center(hipStream_t st, const float* Y32, int DM, const int32_t* sp_off, const int32_t* cnt,
+                   int k, float* mu);
+bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
+                      const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
+                      void* Ym);
+// one block of 256 threads per 128 elements
+bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
+                        const void* Ym);
+
+// ---- global mean -------------------------------------------------------------
+void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
+
+// ---- diagnostics -------------------------------------------------------------
+void launch_uniform(hipStream_t st, uint64_t seed, int64_t gid0, int64_t count, uint32_t stream_id,
+                    double* out);
+
+}  // namespace silh

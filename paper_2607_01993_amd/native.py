@@ -1,0 +1,355 @@
+"""ctypes binding of libsilh.so (the C ABI declared in include/silh.h).
+
+Argument marshalling only: every step of the silhouette path runs in the HIP
+library.  PyTorch provides device memory (through the allocator hooks of the
+C ABI) and the stream the library enqueues on.  There is no fallback: if the
+library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsilh.so")
+
+METRICS = {"eucl": 0, "cos": 1, "manh": 2, "canb": 3}
+PRECS = {"fp32": 0, "bf16": 1, "fp8": 2, "fp32_valu": 3}
+SAMPLERS = {"pps": 0, "uni": 1}
+STATUS = {0: "SILH_OK", 1: "SILH_E_ARG", 2: "SILH_E_LABEL", 3: "SILH_E_K", 4: "SILH_E_STATE",
+          5: "SILH_E_NOMEM", 6: "SILH_E_HIP", 7: "SILH_E_UNSUPPORTED"}
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class SilhParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("metric", ctypes.c_int32), ("prec", ctypes.c_int32), ("sampler", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("t", ctypes.c_int64), ("eps", ctypes.c_double),
+                ("delta", ctypes.c_double), ("seed", ctypes.c_uint64), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
+
+
+class SilhSampleInfo(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int64), ("gid", ctypes.c_void_p),
+                ("offsets_host", ctypes.POINTER(ctypes.c_int64)), ("p", ctypes.c_void_p),
+                ("F0", ctypes.c_int64), ("f0_gid", ctypes.c_void_p), ("f0_W", ctypes.c_void_p),
+                ("f0_offsets_host", ctypes.POINTER(ctypes.c_int64)), ("t", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes), exactly the symbols of include/silh.h
+SIGNATURES = {
+    "silh_sample_init": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "silh_pps_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "silh_weighted_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "silh_scores": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "silh_exact": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_double)]),
+    "silh_sample_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SilhSampleInfo)]),
+    "silh_philox_uniform": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
+    "silh_prof_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "silh_prof_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "silh_prof_count": (ctypes.c_int, []),
+    "silh_prof_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "silh_destroy": (None, [ctypes.c_void_p]),
+    "silh_last_error": (ctypes.c_char_p, []),
+    "silh_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsilh.so (no GPU needed to load it).  Raises if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_01993_amd.build`")
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+        return _lib
+
+
+class SilhError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        msg = load_library().silh_last_error()
+        raise SilhError(status, where, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------------------
+# torch plumbing: device memory through the caching allocator, current stream
+# ---------------------------------------------------------------------------
+_TORCH = None
+
+
+def _torch():
+    global _TORCH
+    if _TORCH is None:
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the silhouette library runs only on the MI355X")
+        _TORCH = torch
+    return _TORCH
+
+
+_alloc_state = threading.local()
+
+
+def _py_alloc(nbytes, user):
+    torch = _torch()
+    dev, stream = _alloc_state.target
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+    except Exception:   # out of memory: the library reports SILH_E_NOMEM
+        return None
+
+
+def _py_free(ptr, user):
+    if ptr and _TORCH is not None:
+        try:
+            _TORCH.cuda.caching_allocator_delete(ptr)
+        except Exception:   # interpreter shutdown: the process frees device memory itself
+            pass
+
+
+_ALLOC_CB = ALLOC_FN(_py_alloc)
+_FREE_CB = FREE_FN(_py_free)
+
+
+class _Target:
+    def __init__(self, device, stream):
+        self.t = (device, stream)
+
+    def __enter__(self):
+        self.prev = getattr(_alloc_state, "target", None)
+        _alloc_state.target = self.t
+
+    def __exit__(self, *a):
+        _alloc_state.target = self.prev
+
+
+def _params(n, d, k, metric, prec, sampler, t, eps, delta, seed, use_torch_alloc=True):
+    p = SilhParams()
+    p.n, p.d, p.k = int(n), int(d), int(k)
+    p.metric = METRICS[metric] if isinstance(metric, str) else int(metric)
+    p.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
+    p.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+    p.reserved0 = 0
+    p.t = int(t)
+    p.eps = float(eps)
+    p.delta = float(delta)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    if use_torch_alloc:
+        p.alloc, p.free = _ALLOC_CB, _FREE_CB
+    else:
+        p.alloc, p.free = ALLOC_FN(), FREE_FN()
+    p.alloc_user = None
+    return p
+
+
+def _check_inputs(X, labels):
+    torch = _torch()
+    if not (X.is_cuda and labels.is_cuda):
+        raise ValueError("X and labels must be device tensors")
+    if X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous float32 [n, d] tensor")
+    if labels.dtype != torch.int32 or labels.dim() != 1 or labels.shape[0] != X.shape[0] \
+            or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 [n] tensor")
+
+
+class Context:
+    """A silh_ctx plus the tensors it references."""
+
+    def __init__(self, ptr, X, labels, params, device, stream):
+        self.ptr = ptr
+        self.X, self.labels = X, labels
+        self.params = params
+        self.device, self.stream = device, stream
+        self.n, self.d, self.k = params.n, params.d, params.k
+
+    def target(self):
+        return _Target(self.device, self.stream)
+
+    def __del__(self):
+        try:
+            silh_destroy(self)
+        except Exception:
+            pass
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s, ctypes.c_void_p(s.cuda_stream)
+
+
+def silh_sample_init(X, labels, k, metric="eucl", prec="fp32", sampler="pps", t=0, eps=0.0,
+                     delta=0.01, seed=0, stream=None, use_torch_alloc=True) -> Context:
+    lib = load_library()
+    _check_inputs(X, labels)
+    s, sh = _stream_handle(stream)
+    p = _params(X.shape[0], X.shape[1], k, metric, prec, sampler, t, eps, delta, seed, use_torch_alloc)
+    out = ctypes.c_void_p()
+    with _Target(X.device.index, s):
+        _check(lib.silh_sample_init(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()),
+                                    ctypes.c_void_p(labels.data_ptr()), sh, ctypes.byref(out)),
+               "silh_sample_init")
+    return Context(out, X, labels, p, X.device.index, s)
+
+
+def silh_pps_sample(ctx: Context):
+    import numpy as np
+    lib = load_library()
+    S = ctypes.c_int64()
+    per = (ctypes.c_int64 * ctx.k)()
+    with ctx.target():
+        _check(lib.silh_pps_sample(ctx.ptr, ctypes.byref(S), per), "silh_pps_sample")
+    return int(S.value), np.frombuffer(per, dtype=np.int64).copy()
+
+
+def silh_weighted_sums(ctx: Context, out=None):
+    torch = _torch()
+    lib = load_library()
+    W = out if out is not None else torch.empty((ctx.n, ctx.k), dtype=torch.float32, device=ctx.X.device)
+    with ctx.target():
+        _check(lib.silh_weighted_sums(ctx.ptr, ctypes.c_void_p(W.data_ptr())), "silh_weighted_sums")
+    return W
+
+
+def silh_scores(ctx: Context, a=True, b=True, s=True, mean=True):
+    torch = _torch()
+    lib = load_library()
+    dev = ctx.X.device
+    outs = {name: torch.empty(ctx.n, dtype=torch.float32, device=dev) if want else None
+            for name, want in (("a", a), ("b", b), ("s", s))}
+    m = ctypes.c_double()
+    ptr = [ctypes.c_void_p(outs[x].data_ptr()) if outs[x] is not None else ctypes.c_void_p()
+           for x in ("a", "b", "s")]
+    with ctx.target():
+        _check(lib.silh_scores(ctx.ptr, *ptr, ctypes.byref(m) if mean else None), "silh_scores")
+    res = {x: v for x, v in outs.items() if v is not None}
+    if mean:
+        res["mean"] = m.value
+    return res
+
+
+def silh_exact(X, labels, k, metric="eucl", prec="fp32", stream=None, a=True, b=True, s=True,
+               mean=True, use_torch_alloc=True):
+    torch = _torch()
+    lib = load_library()
+    _check_inputs(X, labels)
+    st, sh = _stream_handle(stream)
+    p = _params(X.shape[0], X.shape[1], k, metric, prec, "pps", 1, 0.0, 0.5, 0, use_torch_alloc)
+    outs = {name: torch.empty(X.shape[0], dtype=torch.float32, device=X.device) if want else None
+            for name, want in (("a", a), ("b", b), ("s", s))}
+    ptr = [ctypes.c_void_p(outs[x].data_ptr()) if outs[x] is not None else ctypes.c_void_p()
+           for x in ("a", "b", "s")]
+    m = ctypes.c_double()
+    with _Target(X.device.index, st):
+        _check(lib.silh_exact(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()),
+                              ctypes.c_void_p(labels.data_ptr()), sh, *ptr,
+                              ctypes.byref(m) if mean else None), "silh_exact")
+    res = {x: v for x, v in outs.items() if v is not None}
+    if mean:
+        res["mean"] = m.value
+    return res
+
+
+class _DevArray:
+    """Zero-copy wrapper so torch can view library-owned device memory."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr or 0), False), "version": 2}
+
+
+def silh_sample_view(ctx: Context) -> dict:
+    """Copies of the Phase-1 result: sample ids, offsets, p, initial sample."""
+    import numpy as np
+    torch = _torch()
+    lib = load_library()
+    info = SilhSampleInfo()
+    _check(lib.silh_sample_view(ctx.ptr, ctypes.byref(info)), "silh_sample_view")
+    torch.cuda.synchronize()
+    k = ctx.k
+
+    def dev(ptr, count, typestr):
+        if count == 0:
+            return torch.empty(0, dtype=torch.int64 if typestr == "<i8" else torch.float64)
+        return torch.as_tensor(_DevArray(ptr, (count,), typestr), device=ctx.X.device).clone().cpu()
+
+    return {
+        "S": int(info.S), "t": int(info.t),
+        "gid": dev(info.gid, info.S, "<i8").numpy(),
+        "offsets": np.array([info.offsets_host[j] for j in range(k + 1)], dtype=np.int64),
+        "p": dev(info.p, ctx.n, "<f8").numpy(),
+        "F0": int(info.F0),
+        "f0_gid": dev(info.f0_gid, info.F0, "<i8").numpy(),
+        "f0_W": dev(info.f0_W, info.F0, "<f8").numpy(),
+        "f0_offsets": np.array([info.f0_offsets_host[j] for j in range(k + 1)], dtype=np.int64),
+    }
+
+
+def silh_philox_uniform(seed, gid0, count, stream_id, stream=None):
+    torch = _torch()
+    lib = load_library()
+    st, sh = _stream_handle(stream)
+    out = torch.empty(int(count), dtype=torch.float64, device="cuda")
+    _check(lib.silh_philox_uniform(int(seed) & 0xFFFFFFFFFFFFFFFF, int(gid0), int(count), int(stream_id),
+                                   ctypes.c_void_p(out.data_ptr()), sh), "silh_philox_uniform")
+    return out
+
+
+def silh_prof_enable(ctx: Context, on=True):
+    _check(load_library().silh_prof_enable(ctx.ptr, 1 if on else 0), "silh_prof_enable")
+
+
+def silh_prof_reset(ctx: Context):
+    _check(load_library().silh_prof_reset(ctx.ptr), "silh_prof_reset")
+
+
+def silh_prof_get(ctx: Context) -> dict:
+    lib = load_library()
+    res = {}
+    for i in range(lib.silh_prof_count()):
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(lib.silh_prof_get(ctx.ptr, i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)),
+               "silh_prof_get")
+        res[name.value.decode()] = (int(cnt.value), float(ms.value))
+    return res
+
+
+def silh_destroy(ctx: Context):
+    if ctx is not None and ctx.ptr:
+        lib = load_library()
+        with ctx.target():
+            lib.silh_destroy(ctx.ptr)
+        ctx.ptr = None
+
+
+def version() -> str:
+    return load_library().silh_version().decode()

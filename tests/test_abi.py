@@ -1,0 +1,86 @@
+"""The C-ABI library loads, exports every symbol include/silh.h declares, and
+rejects bad arguments before touching the GPU.  CPU only (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_01993_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "silh.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(silh_[a-z_0-9]+)\s*\(", text))
+
+
+def test_header_and_binding_agree():
+    declared = _declared_symbols()
+    assert declared == set(native.SIGNATURES), declared ^ set(native.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.load_library()
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+    assert lib.silh_version().decode().startswith("silh-mi355x")
+    assert lib.silh_prof_count() > 0
+
+
+def test_param_struct_layout():
+    # offsets follow the C declaration order with natural alignment
+    P = native.SilhParams
+    assert P.n.offset == 0 and P.d.offset == 8 and P.k.offset == 12
+    assert P.t.offset == 32 and P.eps.offset == 40 and P.seed.offset == 56
+    assert ctypes.sizeof(P) == 88
+    assert ctypes.sizeof(native.SilhSampleInfo) == 72
+
+
+def _init(**kw):
+    lib = native.load_library()
+    base = dict(n=100, d=4, k=3, metric=0, prec=0, sampler=0, t=10, eps=0.0, delta=0.01, seed=1)
+    base.update(kw)
+    p = native._params(base["n"], base["d"], base["k"], base["metric"], base["prec"], base["sampler"],
+                       base["t"], base["eps"], base["delta"], base["seed"], use_torch_alloc=False)
+    for f in ("reserved0",):
+        if f in kw:
+            setattr(p, f, kw[f])
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    st = lib.silh_sample_init(ctypes.byref(p), fake, fake, None, ctypes.byref(out))
+    return st, lib.silh_last_error().decode(), out
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=1), 1), (dict(d=0), 1), (dict(d=257), 1), (dict(k=1), 1), (dict(k=5000), 1),
+    (dict(metric=7), 1), (dict(prec=9), 1), (dict(sampler=3), 1), (dict(delta=0.0), 1),
+    (dict(delta=1.0), 1), (dict(t=0, eps=0.0), 1), (dict(t=0, eps=1.5), 1),
+    (dict(reserved0=1), 1), (dict(prec=1, metric=2), 7), (dict(prec=2, metric=3), 7), (dict(prec=1, metric=3), 7),
+    (dict(d=200), 7),
+])
+def test_init_rejects_bad_params(kw, status):
+    st, msg, out = _init(**kw)
+    assert st == status, (st, msg)
+    assert msg
+    assert not out.value
+
+
+def test_null_arguments():
+    lib = native.load_library()
+    assert lib.silh_sample_init(None, None, None, None, None) == 1
+    assert lib.silh_pps_sample(None, None, None) == 1
+    assert lib.silh_scores(None, None, None, None, None) == 1
+    assert lib.silh_weighted_sums(None, None) == 1
+    assert lib.silh_sample_view(None, None) == 1
+    assert lib.silh_prof_enable(None, 1) == 1
+    assert lib.silh_philox_uniform(0, -1, 5, 0, None, None) == 1
+    assert lib.silh_philox_uniform(0, 0, 5, 0, None, None) == 1
+    p = native._params(10, 4, 3, 0, 0, 0, 1, 0.0, 0.5, 0, use_torch_alloc=False)
+    p.n = 1
+    assert lib.silh_exact(ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8), None,
+                          None, None, None, None) == 1
+    lib.silh_destroy(None)   # no-op

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 CPU oracle.
+
+Bars: sample index sets bit-exact (a decision may differ only where the
+uniform lies within 1e-12 of the oracle's rate: both sides decide in float64
+but sum W(e_bar) in different orders); float32 a_hat, b_hat within 1e-5
+relative; s_hat and the mean within 4e-5 absolute (Lemma 2 with rho = 1e-5:
+4 rho / (1 - rho))."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2607_01993_amd import native, synth
+
+pytestmark = pytest.mark.gpu
+
+A_B_RTOL = 1e-5
+S_ATOL = 4.0e-5
+# bf16 operands (float32 accumulation): per-element and mean bars
+LOWP_S_ATOL = 1e-2
+LOWP_MEAN_ATOL = 1e-3
+
+
+def dev(X, L):
+    return torch.from_numpy(X).cuda(), torch.from_numpy(L).cuda()
+
+
+def assert_same_sets(smp_o, view, X_n, seed, sampler, t):
+    """Sample sets equal cluster by cluster, up to float64 decision ties."""
+    k = len(smp_o["F"])
+    assert view["S"] == sum(f.shape[0] for f in smp_o["F"])
+    stream = oracle.STREAM_PPS if sampler == "pps" else oracle.STREAM_UNI
+    for j in range(k):
+        g = view["gid"][view["offsets"][j]:view["offsets"][j + 1]]
+        o = smp_o["F"][j]
+        if not np.array_equal(g, o):
+            diff = np.setxor1d(g, o)
+            u = oracle.uniform53(seed, diff.astype(np.uint64), stream)
+            margin = np.abs(u - smp_o["p"][diff])
+            assert np.all(margin < 1e-12), (j, diff[:10], margin[:10])
+
+
+def compare_scores(gpu, ref, rows=None, prec="fp32"):
+    a = gpu["a"].cpu().numpy().astype(np.float64)
+    b = gpu["b"].cpu().numpy().astype(np.float64)
+    s = gpu["s"].cpu().numpy().astype(np.float64)
+    if rows is not None:
+        a, b, s = a[rows], b[rows], s[rows]
+    if prec in ("fp32", "fp32_valu"):
+        np.testing.assert_allclose(a, ref["a"], rtol=A_B_RTOL, atol=1e-30)
+        np.testing.assert_allclose(b, ref["b"], rtol=A_B_RTOL, atol=1e-30)
+        assert np.max(np.abs(s - ref["s"])) <= S_ATOL
+    else:
+        assert np.max(np.abs(s - ref["s"])) <= LOWP_S_ATOL, np.max(np.abs(s - ref["s"]))
+    assert np.all(np.abs(s) <= 1.0)
+
+
+def mean_tol(prec):
+    return S_ATOL if prec in ("fp32", "fp32_valu") else LOWP_MEAN_ATOL
+
+
+# (metric, prec) pairs with a Phase-2 kernel: float32 on the matrix cores for
+# Euclidean / cosine, float32 on the vector ALUs for all, bf16 for Euclidean / cosine
+COMBOS = [("eucl", "fp32"), ("eucl", "fp32_valu"), ("eucl", "bf16"), ("cos", "fp32"),
+          ("cos", "fp32_valu"), ("cos", "bf16"), ("manh", "fp32"), ("canb", "fp32")]
+
+
+# ---------------------------------------------------------------------------
+def test_philox_bit_exact():
+    for seed in (0, 1, 0x1234_5678_9ABC_DEF0):
+        for stream in (0, 1, 2):
+            g0 = 0 if seed else (1 << 32) - 5   # crosses the 32-bit boundary of the id
+            u = native.silh_philox_uniform(seed, g0, 1 << 18, stream).cpu().numpy()
+            ref = oracle.uniform53(seed, np.arange(g0, g0 + (1 << 18), dtype=np.uint64), stream)
+            assert np.array_equal(u, ref)
+
+
+@pytest.mark.parametrize("sampler", ["pps", "uni"])
+def test_small_config_parity(sampler):
+    """n=2,000, d=8, k=4 Gaussian blobs, Euclidean, t=64, seed 0."""
+    X, L = synth.config_small()
+    Xd, Ld = dev(X, L)
+    ctx = native.silh_sample_init(Xd, Ld, 4, "eucl", t=64, delta=0.01, seed=0, sampler=sampler)
+    S, per = native.silh_pps_sample(ctx)
+    view = native.silh_sample_view(ctx)
+    smp = oracle.sample(X, L, 4, "eucl", 64, 0.01, 0, sampler)
+    assert S == view["S"] and per.tolist() == [f.shape[0] for f in smp["F"]]
+    assert_same_sets(smp, view, X.shape[0], 0, sampler, 64)
+    if sampler == "pps":
+        for j in range(4):
+            f0 = view["f0_gid"][view["f0_offsets"][j]:view["f0_offsets"][j + 1]]
+            assert np.array_equal(f0, smp["F0"][j])
+            np.testing.assert_allclose(view["f0_W"][view["f0_offsets"][j]:view["f0_offsets"][j + 1]],
+                                       smp["W0"][j], rtol=1e-13)
+    np.testing.assert_allclose(view["p"], smp["p"], rtol=1e-13)
+    est = oracle.estimate(X, L, 4, "eucl", smp)
+    gpu = native.silh_scores(ctx)
+    compare_scores(gpu, est)
+    assert abs(gpu["mean"] - est["mean"]) <= S_ATOL
+    W = native.silh_weighted_sums(ctx).cpu().numpy()
+    np.testing.assert_allclose(W, est["W"], rtol=A_B_RTOL)
+    native.silh_destroy(ctx)
+
+
+def test_small_config_exact():
+    X, L = synth.config_small()
+    Xd, Ld = dev(X, L)
+    gpu = native.silh_exact(Xd, Ld, 4, "eucl")
+    ref = oracle.exact(X, L, 4, "eucl")
+    compare_scores(gpu, ref)
+    assert abs(gpu["mean"] - ref["mean"]) <= S_ATOL
+
+
+def _ragged_case(metric, n=3001, d=13, k=6, seed=5):
+    # uneven clusters, one singleton (id 4) and one empty cluster (id 5)
+    X, L = synth.tiny_case(n, d, 4, seed=seed)
+    L = L.copy()
+    L[17] = 4
+    if metric == "canb":
+        X = np.abs(X).astype(np.float32)
+        X[:5, :3] = 0.0                      # 0/0 coordinates
+    if metric == "cos":
+        X[3] = 0.0                           # a zero row
+    return X, L, k
+
+
+@pytest.mark.parametrize("metric,prec", COMBOS)
+@pytest.mark.parametrize("sampler", ["pps", "uni"])
+def test_all_metrics_ragged(metric, prec, sampler):
+    X, L, k = _ragged_case(metric)
+    Xd, Ld = dev(X, L)
+    t = 40
+    ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, t=t, delta=0.01, seed=77, sampler=sampler)
+    native.silh_pps_sample(ctx)
+    view = native.silh_sample_view(ctx)
+    smp = oracle.sample(X, L, k, metric, t, 0.01, 77, sampler)
+    assert_same_sets(smp, view, X.shape[0], 77, sampler, t)
+    np.testing.assert_allclose(view["p"], smp["p"], rtol=1e-12)
+    est = oracle.estimate(X, L, k, metric, smp)
+    gpu = native.silh_scores(ctx)
+    compare_scores(gpu, est, prec=prec)
+    assert abs(gpu["mean"] - est["mean"]) <= mean_tol(prec)
+    s = gpu["s"].cpu().numpy()
+    assert s[17] == 0.0                               # singleton
+    W = native.silh_weighted_sums(ctx).cpu().numpy()
+    assert np.all(W[:, 5] == 0.0)                     # empty cluster
+    if prec != "bf16":
+        np.testing.assert_allclose(W[:, :5], est["W"][:, :5], rtol=A_B_RTOL, atol=1e-30)
+    else:
+        np.testing.assert_allclose(W[:, :5], est["W"][:, :5], rtol=5e-3)
+    native.silh_destroy(ctx)
+
+
+@pytest.mark.parametrize("metric,prec", COMBOS)
+def test_exact_all_metrics(metric, prec):
+    X, L, k = _ragged_case(metric, n=1500, d=7)
+    Xd, Ld = dev(X, L)
+    gpu = native.silh_exact(Xd, Ld, k, metric, prec)
+    ref = oracle.exact(X, L, k, metric)
+    compare_scores(gpu, ref, prec=prec)
+    assert abs(gpu["mean"] - ref["mean"]) <= mean_tol(prec)
+
+
+@pytest.mark.parametrize("metric,prec", [("eucl", "fp32"), ("cos", "fp32"), ("eucl", "bf16")])
+@pytest.mark.parametrize("d", [3, 16, 50, 128])
+def test_mfma_dims(metric, prec, d):
+    """Every padded dimension of the MFMA kernel, with n not a multiple of the
+    128-row block."""
+    X, L = synth.tiny_case(1000 + 37 * d, d, 5, seed=d)
+    Xd, Ld = dev(X, L)
+    ctx = native.silh_sample_init(Xd, Ld, 5, metric, prec, t=33, seed=d)
+    native.silh_pps_sample(ctx)
+    smp = oracle.sample(X, L, 5, metric, 33, 0.01, d)
+    est = oracle.estimate(X, L, 5, metric, smp)
+    gpu = native.silh_scores(ctx)
+    compare_scores(gpu, est, prec=prec)
+    assert abs(gpu["mean"] - est["mean"]) <= mean_tol(prec)
+    native.silh_destroy(ctx)
+
+
+def test_large_t_equals_exact():
+    """Algorithm 1: t >= max |C_j| takes every cluster whole (p = 1)."""
+    X, L = synth.tiny_case(1200, 5, 3, seed=9)
+    Xd, Ld = dev(X, L)
+    ctx = native.silh_sample_init(Xd, Ld, 3, "eucl", t=5000, seed=1)
+    S, _ = native.silh_pps_sample(ctx)
+    assert S == 1200
+    view = native.silh_sample_view(ctx)
+    assert np.all(view["p"] == 1.0) and view["F0"] == 0
+    est = native.silh_scores(ctx)
+    ex = native.silh_exact(Xd, Ld, 3, "eucl")
+    for key in ("a", "b", "s"):
+        assert torch.equal(est[key], ex[key])
+    assert est["mean"] == ex["mean"]
+    native.silh_destroy(ctx)
+
+
+def test_resample_is_deterministic():
+    X, L = synth.tiny_case(5000, 6, 5, seed=3)
+    Xd, Ld = dev(X, L)
+    ctx = native.silh_sample_init(Xd, Ld, 5, "manh", t=30, seed=11)
+    native.silh_pps_sample(ctx)
+    v1 = native.silh_sample_view(ctx)
+    r1 = native.silh_scores(ctx)
+    native.silh_pps_sample(ctx)
+    v2 = native.silh_sample_view(ctx)
+    r2 = native.silh_scores(ctx)
+    assert np.array_equal(v1["gid"], v2["gid"]) and np.array_equal(v1["p"], v2["p"])
+    assert torch.equal(r1["s"], r2["s"]) and r1["mean"] == r2["mean"]
+    native.silh_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# error paths reachable from the host
+# ---------------------------------------------------------------------------
+def test_error_paths():
+    X, L = synth.tiny_case(300, 3, 3, seed=1)
+    Xd, Ld = dev(X, L)
+    bad = Ld.clone()
+    bad[10] = 3
+    with pytest.raises(native.SilhError) as e:
+        native.silh_sample_init(Xd, bad, 3, "eucl", t=10)
+    assert e.value.name == "SILH_E_LABEL"
+    neg = Ld.clone()
+    neg[0] = -1
+    with pytest.raises(native.SilhError) as e:
+        native.silh_exact(Xd, neg, 3, "eucl")
+    assert e.value.name == "SILH_E_LABEL"
+    one = torch.zeros_like(Ld)
+    with pytest.raises(native.SilhError) as e:
+        native.silh_sample_init(Xd, one, 3, "eucl", t=10)
+    assert e.value.name == "SILH_E_K"
+    ctx = native.silh_sample_init(Xd, Ld, 3, "eucl", t=10)
+    with pytest.raises(native.SilhError) as e:
+        native.silh_scores(ctx)
+    assert e.value.name == "SILH_E_STATE"
+    with pytest.raises(native.SilhError) as e:
+        native.silh_weighted_sums(ctx)
+    assert e.value.name == "SILH_E_STATE"
+    native.silh_pps_sample(ctx)
+    native.silh_scores(ctx)
+    native.silh_destroy(ctx)
+
+
+def test_allocator_failure_reports_nomem():
+    import ctypes
+    lib = native.load_library()
+    X, L = synth.tiny_case(300, 3, 3, seed=1)
+    Xd, Ld = dev(X, L)
+    p = native._params(300, 3, 3, "eucl", "fp32", "pps", 10, 0.0, 0.01, 0, use_torch_alloc=False)
+    p.alloc = native.ALLOC_FN(lambda nbytes, user: None)
+    p.free = native.FREE_FN(lambda ptr, user: None)
+    out = ctypes.c_void_p()
+    st = lib.silh_sample_init(ctypes.byref(p), ctypes.c_void_p(Xd.data_ptr()),
+                              ctypes.c_void_p(Ld.data_ptr()), None, ctypes.byref(out))
+    assert native.STATUS[st] == "SILH_E_NOMEM"
+    assert not out.value
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# full size: n=1e6, d=32, k=16 Zipf Gaussian blobs, t=256 (the benchmark workload)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def zipf_case():
+    X, L = synth.config_zipf_gauss()
+    return X, L
+
+
+@pytest.mark.parametrize("metric,prec", [("eucl", "fp32"), ("eucl", "bf16"), ("manh", "fp32")])
+def test_full_size_zipf(zipf_case, metric, prec):
+    X, L = zipf_case
+    k, t, seed = 16, 256, 1
+    Xd, Ld = dev(X, L)
+    ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, t=t, delta=0.01, seed=seed)
+    native.silh_pps_sample(ctx)
+    view = native.silh_sample_view(ctx)
+    smp = oracle.sample(X, L, k, metric, t, 0.01, seed, "pps")
+    assert_same_sets(smp, view, X.shape[0], seed, "pps", t)
+    np.testing.assert_allclose(view["p"], smp["p"], rtol=1e-12)
+    gpu = native.silh_scores(ctx)
+    rows = np.random.default_rng(0).choice(X.shape[0], 1500, replace=False)
+    rows = np.sort(np.concatenate([rows, [0, X.shape[0] - 1]]))
+    est = oracle.estimate(X, L, k, metric, smp, rows=rows)
+    compare_scores(gpu, est, rows=rows, prec=prec)
+    # the device mean is the float64 mean of the device scores
+    s = gpu["s"].cpu().numpy().astype(np.float64)
+    assert abs(gpu["mean"] - math.fsum(s.tolist()) / s.shape[0]) < 1e-12
+    native.silh_destroy(ctx)
