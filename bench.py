@@ -163,7 +163,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.prec],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "fp32_valu": "f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"zipf-gauss-blobs n={n} d={d} k={k} t={t} metric={args.metric} "
                                f"prec={args.prec} sampler=pps delta=0.01",

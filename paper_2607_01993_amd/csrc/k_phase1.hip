@@ -11,60 +11,73 @@
 
 namespace silh {
 
-// Distances from x (float32 row, promoted exactly) to NE float64 rows y[e]
-// (row stride d), for the metric M.  Up to EB rows at a time.
-template <int M, int EB>
-__device__ __forceinline__ void dist64_multi(const float* __restrict__ x, int d,
-                                             const double* __restrict__ y, int ne, double out[EB]) {
-  double acc[EB], dot[EB], ny2[EB];
-  double nx2 = 0.0;
+// Distance from x (float32 row held in registers, promoted exactly; zero
+// beyond the true dimension) to one float64 row y (stride DM, zero-padded),
+// for the metric M.  Zero coordinates add exact zeros, so the padding does
+// not change the value.
+template <int M, int DM>
+__device__ __forceinline__ double dist64(const float (&x)[DM], double nx2, const double* __restrict__ y) {
+  double acc = 0.0, dot = 0.0, ny2 = 0.0;
 #pragma unroll
-  for (int e = 0; e < EB; ++e) {
-    acc[e] = 0.0;
-    dot[e] = 0.0;
-    ny2[e] = 0.0;
-  }
-  for (int c = 0; c < d; ++c) {
+  for (int c = 0; c < DM; ++c) {
     const double xc = (double)x[c];
-    if (M == kCos) nx2 = nx2 + xc * xc;
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      if (e < ne) {
-        const double yc = y[(size_t)e * d + c];
-        if (M == kEucl) {
-          const double df = xc - yc;
-          acc[e] = acc[e] + df * df;
-        } else if (M == kManh) {
-          acc[e] = acc[e] + fabs(xc - yc);
-        } else if (M == kCanb) {
-          const double num = fabs(xc - yc);
-          const double den = fabs(xc) + fabs(yc);
-          const double term = den > 0.0 ? num / den : 0.0;
-          acc[e] = acc[e] + term;
-        } else {
-          dot[e] = dot[e] + xc * yc;
-          ny2[e] = ny2[e] + yc * yc;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < EB; ++e) {
+    const double yc = y[c];
     if (M == kEucl) {
-      out[e] = __dsqrt_rn(acc[e]);
-    } else if (M == kCos) {
-      const double den = __dsqrt_rn(nx2) * __dsqrt_rn(ny2[e]);
-      const double sim = den > 0.0 ? dot[e] / den : 0.0;
-      double v = 1.0 - sim;
-      v = v < 0.0 ? 0.0 : (v > 2.0 ? 2.0 : v);
-      out[e] = v;
+      const double df = xc - yc;
+      acc = acc + df * df;
+    } else if (M == kManh) {
+      acc = acc + fabs(xc - yc);
+    } else if (M == kCanb) {
+      const double num = fabs(xc - yc);
+      const double den = fabs(xc) + fabs(yc);
+      const double term = den > 0.0 ? num / den : 0.0;
+      acc = acc + term;
     } else {
-      out[e] = acc[e];
+      dot = dot + xc * yc;
+      ny2 = ny2 + yc * yc;
     }
   }
+  if (M == kEucl) return __dsqrt_rn(acc);
+  if (M == kCos) {
+    const double den = __dsqrt_rn(nx2) * __dsqrt_rn(ny2);
+    const double sim = den > 0.0 ? dot / den : 0.0;
+    const double v = 1.0 - sim;
+    return v < 0.0 ? 0.0 : (v > 2.0 ? 2.0 : v);
+  }
+  return acc;
 }
 
-constexpr int kEB = 8;  // initial-sample rows handled together
+// x row -> registers (vector loads when the row is 16-byte aligned), and its
+// squared norm for the cosine
+template <int M, int DM>
+__device__ __forceinline__ double load_row(const float* __restrict__ X, int d, int g, float (&x)[DM]) {
+  const float* xr = X + (size_t)g * d;
+  if ((d & 3) == 0) {
+#pragma unroll
+    for (int c = 0; c < DM; c += 4) {
+      if (c < d) {
+        const float4 v = *(const float4*)(xr + c);
+        x[c] = v.x;
+        x[c + 1] = v.y;
+        x[c + 2] = v.z;
+        x[c + 3] = v.w;
+      } else {
+        x[c] = x[c + 1] = x[c + 2] = x[c + 3] = 0.0f;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < DM; ++c) x[c] = c < d ? xr[c] : 0.0f;
+  }
+  double nx2 = 0.0;
+  if (M == kCos) {
+#pragma unroll
+    for (int c = 0; c < DM; ++c) nx2 = nx2 + (double)x[c] * (double)x[c];
+  }
+  return nx2;
+}
+
+constexpr int kEB = 4;  // initial-sample rows summed together in the W pass
 
 // ----------------------------------------------------------------------------
 // F^0 draw: sorted position i, element g = perm[i] of cluster j; kept when
@@ -93,7 +106,7 @@ __global__ __launch_bounds__(256) void k_f0_pack(const int32_t* __restrict__ per
                                                  const int32_t* __restrict__ slab,
                                                  const int32_t* __restrict__ flag,
                                                  const int32_t* __restrict__ pos, int n,
-                                                 const float* __restrict__ X, int d,
+                                                 const float* __restrict__ X, int d, int DM,
                                                  int64_t* __restrict__ f0_gid,
                                                  int32_t* __restrict__ f0_cl, double* __restrict__ f0X) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,15 +116,15 @@ __global__ __launch_bounds__(256) void k_f0_pack(const int32_t* __restrict__ per
   f0_gid[dst] = g;
   f0_cl[dst] = slab[i];
   const float* xr = X + (size_t)g * d;
-  double* yr = f0X + (size_t)dst * d;
-  for (int c = 0; c < d; ++c) yr[c] = (double)xr[c];
+  double* yr = f0X + (size_t)dst * DM;
+  for (int c = 0; c < DM; ++c) yr[c] = c < d ? (double)xr[c] : 0.0;
 }
 
 void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
-                    const int32_t* pos, int n, const float* X, int d, int64_t* f0_gid,
+                    const int32_t* pos, int n, const float* X, int d, int DM, int64_t* f0_gid,
                     int32_t* f0_cl, double* f0X) {
   hipLaunchKernelGGL(k_f0_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos,
-                     n, X, d, f0_gid, f0_cl, f0X);
+                     n, X, d, DM, f0_gid, f0_cl, f0X);
 }
 
 // ----------------------------------------------------------------------------
@@ -121,7 +134,7 @@ void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, co
 // a fixed-order block reduction).
 // item layout: [cluster, begin, end, f0_begin, f0_count, partial_base]
 // ----------------------------------------------------------------------------
-template <int M>
+template <int M, int DM>
 __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ items,
                                                    const int32_t* __restrict__ perm,
                                                    const float* __restrict__ X, int d,
@@ -136,11 +149,13 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
 #pragma unroll
     for (int e = 0; e < kEB; ++e) acc[e] = 0.0;
     for (int r = begin + threadIdx.x; r < end; r += 256) {
-      const float* xr = X + (size_t)perm[r] * d;
-      double dv[kEB];
-      dist64_multi<M, kEB>(xr, d, f0X + (size_t)(f0b + e0) * d, ne, dv);
+      float x[DM];
+      const double nx2 = load_row<M, DM>(X, d, perm[r], x);
 #pragma unroll
-      for (int e = 0; e < kEB; ++e) acc[e] = acc[e] + dv[e];
+      for (int e = 0; e < kEB; ++e) {
+        const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
+        acc[e] = acc[e] + dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
+      }
     }
 #pragma unroll
     for (int e = 0; e < kEB; ++e) {
@@ -152,56 +167,71 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
   }
 }
 
-void launch_w_partial(hipStream_t st, int metric, const int32_t* items, int nitems,
+#define SILH_P1_DISPATCH(KERNEL, GRID, ...)                                                   \
+  do {                                                                                        \
+    switch (metric * 8 + (DM == 8 ? 0 : DM == 16 ? 1 : DM == 32 ? 2 : DM == 64 ? 3 : 4)) {    \
+      case 0: hipLaunchKernelGGL((KERNEL<kEucl, 8>), GRID, dim3(256), 0, st, __VA_ARGS__); break;   \
+      case 1: hipLaunchKernelGGL((KERNEL<kEucl, 16>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 2: hipLaunchKernelGGL((KERNEL<kEucl, 32>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 3: hipLaunchKernelGGL((KERNEL<kEucl, 64>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 4: hipLaunchKernelGGL((KERNEL<kEucl, 128>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 8: hipLaunchKernelGGL((KERNEL<kCos, 8>), GRID, dim3(256), 0, st, __VA_ARGS__); break;    \
+      case 9: hipLaunchKernelGGL((KERNEL<kCos, 16>), GRID, dim3(256), 0, st, __VA_ARGS__); break;   \
+      case 10: hipLaunchKernelGGL((KERNEL<kCos, 32>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 11: hipLaunchKernelGGL((KERNEL<kCos, 64>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 12: hipLaunchKernelGGL((KERNEL<kCos, 128>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 16: hipLaunchKernelGGL((KERNEL<kManh, 8>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 17: hipLaunchKernelGGL((KERNEL<kManh, 16>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 18: hipLaunchKernelGGL((KERNEL<kManh, 32>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 19: hipLaunchKernelGGL((KERNEL<kManh, 64>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 20: hipLaunchKernelGGL((KERNEL<kManh, 128>), GRID, dim3(256), 0, st, __VA_ARGS__); break;\
+      case 24: hipLaunchKernelGGL((KERNEL<kCanb, 8>), GRID, dim3(256), 0, st, __VA_ARGS__); break;  \
+      case 25: hipLaunchKernelGGL((KERNEL<kCanb, 16>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 26: hipLaunchKernelGGL((KERNEL<kCanb, 32>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      case 27: hipLaunchKernelGGL((KERNEL<kCanb, 64>), GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<kCanb, 128>), GRID, dim3(256), 0, st, __VA_ARGS__); break;\
+    }                                                                                         \
+  } while (0)
+
+void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, int nitems,
                       const int32_t* perm, const float* X, int d, const double* f0X, double* partial) {
   if (nitems <= 0) return;
-  switch (metric) {
-    case kEucl:
-      hipLaunchKernelGGL(k_w_partial<kEucl>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
-      break;
-    case kCos:
-      hipLaunchKernelGGL(k_w_partial<kCos>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
-      break;
-    case kManh:
-      hipLaunchKernelGGL(k_w_partial<kManh>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
-      break;
-    default:
-      hipLaunchKernelGGL(k_w_partial<kCanb>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial);
-      break;
-  }
+  SILH_P1_DISPATCH(k_w_partial, dim3(nitems), items, perm, X, d, f0X, partial);
 }
 
-// W(e_bar): sum of its cluster's item partials, in item order.
-__global__ __launch_bounds__(256) void k_w_final(const int32_t* __restrict__ f0_cl, int F0,
+// W(e_bar): sum of its cluster's item partials.  One block per initial
+// element; threads take items in a fixed stride, then a fixed-order block sum.
+__global__ __launch_bounds__(256) void k_w_final(const int32_t* __restrict__ f0_cl,
                                                  const int32_t* __restrict__ f0_off,
                                                  const int32_t* __restrict__ citem_first,
                                                  const int32_t* __restrict__ citem_count,
                                                  const int32_t* __restrict__ items,
                                                  const double* __restrict__ partial,
                                                  double* __restrict__ W) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F0) return;
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
   const int j = f0_cl[i];
   const int local = i - f0_off[j];
   const int first = citem_first[j], cnt = citem_count[j];
   double s = 0.0;
-  for (int q = 0; q < cnt; ++q) s = s + partial[items[(size_t)(first + q) * 6 + 5] + local];
-  W[i] = s;
+  for (int q = threadIdx.x; q < cnt; q += 256) s = s + partial[items[(size_t)(first + q) * 6 + 5] + local];
+  const double tot = block_sum_f64<256>(s, sh);
+  if (threadIdx.x == 0) W[i] = tot;
 }
 
 void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off,
                     const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
                     const double* partial, double* W) {
   if (F0 <= 0) return;
-  hipLaunchKernelGGL(k_w_final, dim3((int)ceil_div(F0, 256)), dim3(256), 0, st, f0_cl, F0, f0_off,
-                     citem_first, citem_count, items, partial, W);
+  hipLaunchKernelGGL(k_w_final, dim3(F0), dim3(256), 0, st, f0_cl, f0_off, citem_first, citem_count,
+                     items, partial, W);
 }
 
 // ----------------------------------------------------------------------------
 // gamma_e, p_e and the final Poisson draw (PPS), or the uniform rate t/|C_j|.
 // Clusters with |C_j| <= t are taken whole with p = 1.
 // ----------------------------------------------------------------------------
-template <int M>
+template <int M, int DM>
 __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __restrict__ perm,
                                               const int32_t* __restrict__ slab, int n,
                                               const float* __restrict__ X, int d,
@@ -227,20 +257,14 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
   } else {
     double gam = 1.0 / (double)m;
     const int fb = f0_off[j], fe = f0_off[j + 1];
-    const float* xr = X + (size_t)g * d;
-    for (int e0 = fb; e0 < fe; e0 += kEB) {
-      const int ne = fe - e0 < kEB ? fe - e0 : kEB;
-      double dv[kEB];
-      dist64_multi<M, kEB>(xr, d, f0X + (size_t)e0 * d, ne, dv);
-#pragma unroll
-      for (int e = 0; e < kEB; ++e) {
-        if (e < ne) {
-          const double w = W[e0 + e];
-          if (w > 0.0) {
-            const double r = dv[e] / w;
-            gam = r > gam ? r : gam;
-          }
-        }
+    float x[DM];
+    const double nx2 = load_row<M, DM>(X, d, g, x);
+    for (int e = fb; e < fe; ++e) {
+      const double w = W[e];
+      const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)e * DM);
+      if (w > 0.0) {
+        const double r = dv / w;
+        gam = r > gam ? r : gam;
       }
     }
     p = (double)t * gam;
@@ -251,25 +275,12 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
   flag[i] = sel;
 }
 
-void launch_draw(hipStream_t st, int metric, int sampler, const int32_t* perm, const int32_t* slab,
-                 int n, const float* X, int d, const int32_t* csize, int64_t t, uint64_t seed,
-                 const int32_t* f0_off, const double* f0X, const double* W, double* p_gid,
-                 int32_t* flag) {
-  const dim3 g((int)ceil_div(n, 256)), b(256);
-  switch (metric) {
-    case kEucl:
-      hipLaunchKernelGGL(k_draw<kEucl>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
-      break;
-    case kCos:
-      hipLaunchKernelGGL(k_draw<kCos>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
-      break;
-    case kManh:
-      hipLaunchKernelGGL(k_draw<kManh>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
-      break;
-    default:
-      hipLaunchKernelGGL(k_draw<kCanb>, g, b, 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag);
-      break;
-  }
+void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t* perm,
+                 const int32_t* slab, int n, const float* X, int d, const int32_t* csize, int64_t t,
+                 uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
+                 double* p_gid, int32_t* flag) {
+  SILH_P1_DISPATCH(k_draw, dim3((int)ceil_div(n, 256)), sampler, perm, slab, n, X, d, csize, t, seed,
+                   f0_off, f0X, W, p_gid, flag);
 }
 
 // exact silhouette: every element kept with p = 1

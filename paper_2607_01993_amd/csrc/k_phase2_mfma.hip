@@ -37,7 +37,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
-constexpr int kCenterRows = 1024;
+constexpr int kCenterRows = 256;
 
 __host__ __device__ constexpr int round_up_c(int a, int b) { return (a + b - 1) / b * b; }
 
@@ -69,23 +69,35 @@ __device__ __forceinline__ void split3(float v, float& h, float& m, float& l) {
 // (float64 sums; any point of the cluster would do, the mean keeps the
 // centred operands smallest)
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_center(const float* __restrict__ Y32, int DM,
+__global__ __launch_bounds__(256) void k_center(const float* __restrict__ Y32, int DM, int KP,
                                                 const int32_t* __restrict__ sp_off,
                                                 const int32_t* __restrict__ cnt,
                                                 float* __restrict__ mu) {
+  __shared__ double part[256];
   const int j = blockIdx.x;
   const int m = cnt[j] < kCenterRows ? cnt[j] : kCenterRows;
   const int base = sp_off[j];
-  for (int c = threadIdx.x; c < DM; c += blockDim.x) {
+  // coordinate chunks of up to 32 columns; 8 row groups per chunk
+  const int cc = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  for (int c0 = 0; c0 < KP; c0 += 32) {
+    const int c = c0 + cc;
     double s = 0.0;
-    for (int r = 0; r < m; ++r) s += (double)Y32[(size_t)(base + r) * DM + c];
-    mu[(size_t)j * DM + c] = m > 0 ? (float)(s / m) : 0.0f;
+    if (c < DM)
+      for (int r = rg; r < m; r += 8) s += (double)Y32[(size_t)(base + r) * DM + c];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (rg == 0 && c < KP) {
+      double t = 0.0;
+      for (int g = 0; g < 8; ++g) t += part[g * 32 + cc];
+      mu[(size_t)j * KP + c] = (m > 0 && c < DM) ? (float)(t / m) : 0.0f;
+    }
+    __syncthreads();
   }
 }
 
-void launch_center(hipStream_t st, const float* Y32, int DM, const int32_t* sp_off, const int32_t* cnt,
-                   int k, float* mu) {
-  hipLaunchKernelGGL(k_center, dim3(k), dim3(256), 0, st, Y32, DM, sp_off, cnt, mu);
+void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32_t* sp_off,
+                   const int32_t* cnt, int k, float* mu) {
+  hipLaunchKernelGGL(k_center, dim3(k), dim3(256), 0, st, Y32, DM, KP, sp_off, cnt, mu);
 }
 
 // ----------------------------------------------------------------------------
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
   for (int c = 0; c < C::KP; ++c) row[c] = 0.f;
   if (real) {
     const float* y = Y32 + (size_t)s * DM;
-    const float* m = mu + (size_t)j * DM;
+    const float* m = mu + (size_t)j * C::KP;
     float ny = 0.f;
 #pragma unroll
     for (int c = 0; c < DM; ++c) {
@@ -148,9 +160,27 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
 }
 
 // ----------------------------------------------------------------------------
-// 16 per-lane row sums, each over the lane's column: after the exchanges lane
-// l holds the sum over all 32 columns for row r = (l >> 1) & 15 of its half.
+// 16 per-lane row sums, each over the lane's column: five exchange steps, each
+// pairing lanes that differ in one bit of the column index and halving the
+// number of live values (the partner receives the half it keeps).  Partners:
+// lane ^ 16 by ds_swizzle, then within 16-lane rows by DPP (rotate by 8,
+// mirror inside 8, quad permutations), which pair lanes that differ in bit 3,
+// bit 2, bit 1 and bit 0 respectively.  Afterwards lane l holds the sum over
+// all 32 columns for row r = (l >> 1) & 15 of its half (lanes l and l^1 agree).
 // ----------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float swz_xor16(float v) {
+  // BitMode swizzle inside 32 lanes: and 0x1f, or 0, xor 0x10
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+constexpr int kDppRor8 = 0x128;        // row_ror:8      -> lane ^ 8 inside 16
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: 7 - (lane & 7)
+constexpr int kDppQuad2301 = 0x4E;     // quad_perm [2,3,0,1] -> lane ^ 2
+constexpr int kDppQuad1032 = 0xB1;     // quad_perm [1,0,3,2] -> lane ^ 1
+
 __device__ __forceinline__ float transpose_reduce16(float (&v)[16], int lane) {
   {
     const bool up = lane & 16;
@@ -158,7 +188,7 @@ __device__ __forceinline__ float transpose_reduce16(float (&v)[16], int lane) {
     for (int i = 0; i < 8; ++i) {
       const float send = up ? v[i] : v[i + 8];
       const float keep = up ? v[i + 8] : v[i];
-      v[i] = keep + __shfl_xor(send, 16, kWave);
+      v[i] = keep + swz_xor16(send);
     }
   }
   {
@@ -167,7 +197,7 @@ __device__ __forceinline__ float transpose_reduce16(float (&v)[16], int lane) {
     for (int i = 0; i < 4; ++i) {
       const float send = up ? v[i] : v[i + 4];
       const float keep = up ? v[i + 4] : v[i];
-      v[i] = keep + __shfl_xor(send, 8, kWave);
+      v[i] = keep + dpp_f<kDppRor8>(send);
     }
   }
   {
@@ -176,16 +206,16 @@ __device__ __forceinline__ float transpose_reduce16(float (&v)[16], int lane) {
     for (int i = 0; i < 2; ++i) {
       const float send = up ? v[i] : v[i + 2];
       const float keep = up ? v[i + 2] : v[i];
-      v[i] = keep + __shfl_xor(send, 4, kWave);
+      v[i] = keep + dpp_f<kDppHalfMirror>(send);
     }
   }
   {
     const bool up = lane & 2;
     const float send = up ? v[0] : v[1];
     const float keep = up ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 2, kWave);
+    v[0] = keep + dpp_f<kDppQuad2301>(send);
   }
-  return v[0] + __shfl_xor(v[0], 1, kWave);
+  return v[0] + dpp_f<kDppQuad1032>(v[0]);
 }
 
 template <int P, int DM>
@@ -199,20 +229,53 @@ struct AFrag<1, DM> {
   bf16x8 v[MCfg<1, DM>::NSTEP];
 };
 
+template <int P, int DM>
+struct BFrag;
+template <int DM>
+struct BFrag<0, DM> {
+  float2 v[MCfg<0, DM>::NSTEP / 2];
+};
+template <int DM>
+struct BFrag<1, DM> {
+  bf16x8 v[MCfg<1, DM>::NSTEP];
+};
+
+// one tile's B operand (this lane's half row), weight and element id
+template <int P, int DM>
+__device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const float* __restrict__ w,
+                                          const int32_t* __restrict__ gid_pk, int row0, int lane_off,
+                                          int col, BFrag<P, DM>& b, float& wj, int& gj) {
+  using C = MCfg<P, DM>;
+  if constexpr (P == 0) {
+    const float2* bp = (const float2*)((const float*)Ym + (size_t)row0 * C::KP + lane_off);
+#pragma unroll
+    for (int s2 = 0; s2 < C::NSTEP / 2; ++s2) b.v[s2] = bp[s2];
+  } else {
+    const bf16x8* bp = (const bf16x8*)((const __bf16*)Ym + (size_t)row0 * C::KP + lane_off);
+#pragma unroll
+    for (int s = 0; s < C::NSTEP; ++s) b.v[s] = bp[s];
+  }
+  wj = w[row0 + col];
+  gj = gid_pk[row0 + col];
+}
+
 template <int M, int P, int DM>
 __global__ __launch_bounds__(256) void k_p2_mfma(
     const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
-    const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ sp_off,
-    const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
-    const float* __restrict__ mu, float* __restrict__ a_out, float* __restrict__ b_out,
-    float* __restrict__ s_out, float* __restrict__ What, double* __restrict__ bpart) {
+    const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
+    const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt,
+    const int32_t* __restrict__ csize, int k, const float* __restrict__ mu,
+    float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
+    float* __restrict__ What, double* __restrict__ bpart) {
   using C = MCfg<P, DM>;
+  // the augmentation columns always fall in the upper half of the row
+  constexpr int AUG0 = DM - C::HALF;
+  static_assert(AUG0 >= 0 && AUG0 + C::AUG <= C::HALF, "augmentation placement");
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
   const int col = lane & 31;
-  const int P0 = (blockIdx.x * 4 + wave) * 32;
+  const int P0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * 32);
 
   // this lane's half of its A row (raw or unit-scaled), zero outside [0, d)
   const int pa = P0 + col < n ? P0 + col : n - 1;
@@ -237,6 +300,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     for (int i = 0; i < C::HALF; ++i) xr[i] *= rx;
   }
   const float alpha = M == kCos ? 0.5f : 1.0f;
+  const int lane_off = col * C::KP + h * C::HALF;
 
   // the element whose sums this lane ends up holding (twice: lanes l, l^1)
   const int rr = (lane >> 1) & 15;
@@ -250,21 +314,18 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   AFrag<P, DM> A;
 
   for (int j = 0; j < k; ++j) {
-    // ---- A operand for cluster j: x~ = x - mu_j, rounded, + augmentation
+    // ---- A operand for cluster j: x~ = x - mu_j (mu zero-padded to KP),
+    // rounded to the input precision, plus the augmentation
     {
-      const float* m = mu + (size_t)j * DM;
+      const float* m = mu + (size_t)j * C::KP + h * C::HALF;
       float xq[C::HALF];
       float part = 0.f;
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) {
-        const int c = h * C::HALF + i;
-        float v = 0.f;
-        if (c < DM) {
-          v = xr[i] - m[c];
-          if (P == 1) v = q_bf16(v);
-          part = fmaf(v, v, part);
-        }
+        float v = xr[i] - m[i];
+        if (P == 1) v = q_bf16(v);
         xq[i] = v;
+        part = fmaf(v, v, part);
       }
       const float nx = part + __shfl_xor(part, 32, kWave);
       const float an = fmaf(alpha, nx, ux);
@@ -277,12 +338,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         aug[3] = aug[4] = aug[5] = 1.0f;
       }
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) {
-        const int c = h * C::HALF + i;
-#pragma unroll
-        for (int q = 0; q < C::AUG; ++q)
-          if (c == DM + q) xq[i] = aug[q];
-      }
+      for (int q = 0; q < C::AUG; ++q) xq[AUG0 + q] = h ? aug[q] : xq[AUG0 + q];
       if constexpr (P == 0) {
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s) A.v[s] = xq[s];
@@ -294,7 +350,8 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       }
     }
 
-    // ---- sweep the cluster's sample tiles
+    // ---- sweep the cluster's sample tiles (B operand double-buffered: the
+    // next tile's loads are issued before this tile's MFMAs)
     const int base = sp_off[j];
     const int ntile = (cnt[j] + 31) >> 5;
     double wsum = 0.0;
@@ -302,24 +359,33 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
     int g = 0;
-    for (int t = 0; t < ntile; ++t) {
-      const int srow = base + t * 32 + col;
-      const float wj = w[srow];
+    auto tile = [&](const BFrag<P, DM>& bf, float wj, int gj, bool last) {
       f32x16 c;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) c[r] = 0.f;
       if constexpr (P == 0) {
-        const float2* bp = (const float2*)((const float*)Ym + (size_t)srow * C::KP + h * C::HALF);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[0], bf.v[0].x, f32x16{}, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[1], bf.v[0].y, c, 0, 0, 0);
 #pragma unroll
-        for (int s2 = 0; s2 < C::NSTEP / 2; ++s2) {
-          const float2 bv = bp[s2];
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2], bv.x, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2 + 1], bv.y, c, 0, 0, 0);
+        for (int s2 = 1; s2 < C::NSTEP / 2; ++s2) {
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2], bf.v[s2].x, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2 + 1], bf.v[s2].y, c, 0, 0, 0);
         }
       } else {
-        const bf16x8* bp = (const bf16x8*)((const __bf16*)Ym + (size_t)srow * C::KP + h * C::HALF);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v[0], bf.v[0], f32x16{}, 0, 0, 0);
 #pragma unroll
-        for (int s = 0; s < C::NSTEP; ++s) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v[s], bp[s], c, 0, 0, 0);
+        for (int s = 1; s < C::NSTEP; ++s)
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v[s], bf.v[s], c, 0, 0, 0);
+      }
+      if (M == kEucl) {
+        // d(e, e) = 0 exactly: the expanded form leaves rounding noise there,
+        // which the square root would amplify.  Only a column holding one of
+        // this wave's own 32 elements (in this lane's half) is touched.
+        const int self = gj - P0;
+        if ((unsigned)self < 32u && ((self >> 2) & 1) == h) {
+          const int rh = ((self >> 3) << 2) | (self & 3);
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (r == rh) c[r] = 0.0f;
+        }
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -330,11 +396,23 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
           dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, 2.0f);
         acc[r] = fmaf(wj, dv, acc[r]);
       }
-      if (++g == kFold || t == ntile - 1) {
+      if (++g == kFold || last) {
         wsum += (double)transpose_reduce16(acc, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.f;
         g = 0;
+      }
+    };
+    BFrag<P, DM> b0, b1;
+    float w0 = 0.f, w1 = 0.f;
+    int g0 = -1, g1 = -1;
+    if (ntile > 0) load_tile<P, DM>(Ym, w, gid_pk, base, lane_off, col, b0, w0, g0);
+    for (int t = 0; t < ntile; t += 2) {
+      if (t + 1 < ntile) load_tile<P, DM>(Ym, w, gid_pk, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
+      tile(b0, w0, g0, t + 1 == ntile);
+      if (t + 1 < ntile) {
+        if (t + 2 < ntile) load_tile<P, DM>(Ym, w, gid_pk, base + (t + 2) * 32, lane_off, col, b0, w0, g0);
+        tile(b1, w1, g1, t + 2 == ntile);
       }
     }
     if (What != nullptr && pvalid && (lane & 1) == 0) What[(size_t)pout * k + j] = (float)wsum;
@@ -365,7 +443,7 @@ template <int M, int P, int DM>
 static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym) {
   const int blocks = (int)ceil_div(A.n, 128);
   hipLaunchKernelGGL((k_p2_mfma<M, P, DM>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
-                     A.w, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart);
+                     A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart);
 }
 
 template <int M, int P, int DM>

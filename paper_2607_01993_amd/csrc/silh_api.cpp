@@ -398,14 +398,14 @@ silh_status compact_and_pack(silh_ctx* c) {
   if (c->mfma && c->S_pad > 0) {
     const int prec = c->prm.prec == SILH_BF16 ? 1 : 0;
     const int KP = mfma_kp(prec, c->DM);
-    CHK(dalloc(c, c->alloc_sample, &c->mu, (size_t)k * c->DM));
+    CHK(dalloc(c, c->alloc_sample, &c->mu, (size_t)k * KP));
     void* ym = raw_alloc(c, (size_t)c->S_pad * KP * (prec ? 2 : 4));
     if (!ym) return fail(SILH_E_NOMEM, "device allocation of the packed sample failed");
     c->alloc_sample.push_back(ym);
     c->Ym = ym;
     {
       Launch L(c, K_CENTER);
-      launch_center(c->st, c->Y32, c->DM, c->sp_off, c->cnt, k, c->mu);
+      launch_center(c->st, c->Y32, c->DM, KP, c->sp_off, c->cnt, k, c->mu);
       CHK(L.done());
     }
     {
@@ -465,12 +465,13 @@ silh_status phase1(silh_ctx* c) {
   }
   CHK(dalloc(c, c->alloc_sample, &c->f0_gid, (size_t)c->F0));
   CHK(dalloc(c, c->alloc_sample, &c->f0_cl, (size_t)c->F0));
-  CHK(dalloc(c, c->alloc_sample, &c->f0X, (size_t)c->F0 * d));
+  CHK(dalloc(c, c->alloc_sample, &c->f0X, (size_t)c->F0 * c->DM));
   CHK(dalloc(c, c->alloc_sample, &c->W0, (size_t)c->F0));
   if (pps && c->F0 > 0) {
     {
       Launch L(c, K_F0_PACK);
-      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->f0_gid, c->f0_cl, c->f0X);
+      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, c->f0_gid, c->f0_cl,
+                     c->f0X);
       CHK(L.done());
     }
     // work items for W(e_bar)
@@ -500,7 +501,8 @@ silh_status phase1(silh_ctx* c) {
     CHK(h2d(c, c->citem_count, c->citem_count_h));
     {
       Launch L(c, K_W_PARTIAL);
-      launch_w_partial(c->st, c->prm.metric, c->items, nitems, c->perm, c->X, d, c->f0X, c->partial);
+      launch_w_partial(c->st, c->prm.metric, c->DM, c->items, nitems, c->perm, c->X, d, c->f0X,
+                       c->partial);
       CHK(L.done());
     }
     {
@@ -512,7 +514,7 @@ silh_status phase1(silh_ctx* c) {
   }
   {
     Launch L(c, K_DRAW);
-    launch_draw(c->st, c->prm.metric, pps ? 0 : 1, c->perm, c->slab, n, c->X, d, c->csize, c->t,
+    launch_draw(c->st, c->prm.metric, c->DM, pps ? 0 : 1, c->perm, c->slab, n, c->X, d, c->csize, c->t,
                 c->prm.seed, c->f0_off, c->f0X, c->W0, c->p_gid, c->flag);
     CHK(L.done());
   }
@@ -528,6 +530,7 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
   A.Y = c->Y32;
   A.w = c->w32;
   A.aux = c->aux32;
+  A.gid_pk = c->gid_pk;
   A.sp_off = c->sp_off;
   A.cnt = c->cnt;
   A.csize = c->csize;

@@ -11,7 +11,7 @@ constexpr int kSortSeg = 1024;
 // Elements per block of the int32 exclusive scan (256 threads x 8).
 constexpr int kScanTile = 2048;
 // Members per work item of the W(e_bar) partial sums.
-constexpr int kWChunk = 2048;
+constexpr int kWChunk = 512;
 // Sample rows of each cluster are padded to a multiple of this.
 constexpr int kSamplePad = 32;
 // Rows per Phase-2 block in the VALU kernel.
@@ -35,19 +35,20 @@ void launch_gather_at(hipStream_t st, const int32_t* scan, const int32_t* off, i
 void launch_f0_flag(hipStream_t st, const int32_t* perm, const int32_t* slab, int n,
                     const int32_t* csize, const double* q, int64_t t, uint64_t seed, int32_t* flag);
 void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
-                    const int32_t* pos, int n, const float* X, int d, int64_t* f0_gid,
+                    const int32_t* pos, int n, const float* X, int d, int DM, int64_t* f0_gid,
                     int32_t* f0_cl, double* f0X);
 // one block per work item: item = (cluster, first sorted pos, end sorted pos,
 // first F0 index of the cluster, |F0_j|, base in `partial`)
-void launch_w_partial(hipStream_t st, int metric, const int32_t* items, int nitems,
+// f0X rows have stride DM (zero-padded)
+void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, int nitems,
                       const int32_t* perm, const float* X, int d, const double* f0X, double* partial);
 void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off,
                     const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
                     const double* partial, double* W);
-void launch_draw(hipStream_t st, int metric, int sampler, const int32_t* perm, const int32_t* slab,
-                 int n, const float* X, int d, const int32_t* csize, int64_t t, uint64_t seed,
-                 const int32_t* f0_off, const double* f0X, const double* W, double* p_gid,
-                 int32_t* flag);
+void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t* perm,
+                 const int32_t* slab, int n, const float* X, int d, const int32_t* csize, int64_t t,
+                 uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
+                 double* p_gid, int32_t* flag);
 void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, int32_t* flag);
 // Scatter the selected elements into the cluster-blocked, padded sample.
 // mode 0: raw coordinates; 1: rows scaled to unit L2 norm (cosine).
@@ -64,6 +65,7 @@ struct P2Args {
   const float* Y;      // [S_pad][DM]
   const float* w;      // [S_pad]
   const float* aux;    // [S_pad] cosine: 0.5 for a zero sample vector, else 0
+  const int32_t* gid_pk;  // [S_pad] element id of each packed sample row, -1 for padding
   const int32_t* sp_off;  // [k+1] padded sample offsets
   const int32_t* cnt;     // [k] |F_j|
   const int32_t* csize;   // [k] |C_j|
@@ -80,8 +82,9 @@ int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if u
 
 // MFMA path (Euclidean, cosine; float32 or bf16 operands)
 int mfma_kp(int prec, int DM);   // contraction length of a packed row
-void launch_center(hipStream_t st, const float* Y32, int DM, const int32_t* sp_off, const int32_t* cnt,
-                   int k, float* mu);
+// mu: [k][KP] centres, zero beyond DM
+void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32_t* sp_off,
+                   const int32_t* cnt, int k, float* mu);
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
                       void* Ym);

