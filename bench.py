@@ -1,12 +1,17 @@
-"""Benchmark: one step = the whole sampled-silhouette hot path on one GPU --
-cluster index, Phase 1 (PPS sampling, float64), sample packing, Phase 2
-(weighted sums, a_hat, b_hat, s_hat) and the float64 global mean -- on the
-n=1e6, d=32, k=16 Zipf Gaussian-blob workload with t=256 samples per cluster.
+"""Benchmark of the sampled-silhouette hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--metric eucl] [--prec fp32]
+One step = one silhouette request end to end on the GPU: cluster index,
+Phase 1 (PPS sampling, float64), sample packing, Phase 2 (weighted sums,
+a_hat, b_hat, s_hat) and the float64 global mean, on the workload
+n = 1e6, d = 32, k = 16 Gaussian blobs with Zipf(1.1) sizes, t = 256
+samples per cluster, Euclidean distance.  The timed precision is bf16 MFMA
+(float32 accumulation); the same steps in float32 give |delta s_mean|.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--metric eucl] [--prec bf16]
 
 Prints one JSON line.  `value` is weighted distance evaluations per second of
-the whole step: (n*S + sum_j |C_j| |F0_j|) / step time, inputs resident in HBM.
+the whole step: (n*S + sum_j |C_j| |F0_j|) / step time, with the inputs
+resident in HBM before the timed region.
 """
 from __future__ import annotations
 
@@ -21,27 +26,64 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {  # published MI355X figures
+# MI355X figures: published peaks, and unit-count derivations from them
+# (256 CUs at 2.4 GHz).  157.3 TFLOP/s fp32 vector = 128 fp32 lanes / clk / CU
+# doing FMAs; transcendental instructions (v_sqrt_f32) issue at a quarter of
+# that, 32 lanes / clk / CU.
+CU, CLK = 256, 2.4e9
+PEAK = {
     "hbm_gbs": 8000.0,
     "fp32_vec_tflops": 157.3,
-    "bf16_tflops": 2500.0,
-    "fp8_tflops": 5000.0,
+    "bf16_mfma_tflops": 2500.0,
+    "fp8_mfma_tflops": 5000.0,
     "fp32_mfma_tflops": 157.3,
+    "sqrt_tops": CU * 32 * CLK / 1e12,   # 19.66 T square roots / s
+}
+WORKLOAD = dict(n=1_000_000, d=32, k=16, t=256, seed=1)
+
+# HBM bytes per Phase-2 launch on this workload from the two rocprofv3 PMC
+# runs (FETCH_SIZE, WRITE_SIZE; scaled by a 256 MiB copy), valid only for the
+# kernel source they were taken with (sha256 prefix of the source file).
+TRAFFIC = {
+    ("eucl", "bf16"): {"src": "paper_2607_01993_amd/csrc/k_phase2_mfma.hip", "sha256": "81dc4c04e5e2beb5",
+                       "bytes": (136.2 + 12.3) * 1e6,
+                       "profile": "profiles/hbm_traffic_zipf_n1e6_d32_k16_t256.md"},
 }
 
 
-def flops_per_pair(metric: str, prec: str, d: int) -> float:
-    """Algorithmic flops of one weighted distance evaluation (Phase 2 pair):
-    the distance itself plus the multiply-add by the weight."""
-    if metric == "eucl":
-        return 3.0 * d + 1.0 + 2.0      # (x-y), square, add per coordinate; sqrt; w*d + acc
-    if metric == "cos":
-        return 2.0 * d + 2.0 + 2.0      # multiply-add per coordinate; 1 - dot*rx; w*d + acc
-    if metric == "manh":
-        return 2.0 * d + 2.0            # (x-y), add of |.| per coordinate; w*d + acc
-    if metric == "canb":
-        return 5.0 * d + 2.0            # sub, |x|+|y|, divide, |.|, add per coordinate; w*d + acc
-    raise ValueError(metric)
+def traffic_for(metric, prec):
+    import hashlib
+    rec = TRAFFIC.get((metric, prec))
+    if rec is None:
+        return None
+    with open(os.path.join(ROOT, rec["src"]), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return rec["bytes"] if sha == rec["sha256"] else None
+
+
+def phase2_roofline(metric, prec, d, n, S, kern_s):
+    """Roofline of the Phase-2 launch: algorithmic work per launch (n*S pairs
+    times the per-pair figure) over the average launch duration."""
+    pairs = float(n) * S
+    if metric == "eucl" and prec == "bf16":
+        # bound by the square root per pair (transcendental rate); the MFMA
+        # contraction (2d flops per pair) is reported beside it
+        ach = pairs / kern_s / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": PEAK["sqrt_tops"], "unit": "TFLOP/s",
+                "frac": ach / PEAK["sqrt_tops"], "work": "1 square root per pair (counted as 1 flop)",
+                "mfma": {"achieved": 2 * d * pairs / kern_s / 1e12, "peak": PEAK["bf16_mfma_tflops"],
+                         "unit": "TFLOP/s", "frac": 2 * d * pairs / kern_s / 1e12 / PEAK["bf16_mfma_tflops"]}}
+    if metric in ("eucl", "cos") and prec in ("fp32", "bf16"):
+        pk = PEAK["fp32_mfma_tflops"] if prec == "fp32" else PEAK["bf16_mfma_tflops"]
+        ach = 2 * d * pairs / kern_s / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
+                "work": f"2d = {2 * d} MFMA flops per pair"}
+    # vector-ALU metrics: per pair and coordinate sub + add (Manhattan) or
+    # sub, add, max, reciprocal, fma (Canberra); plus the weight fma
+    per = {"manh": 2 * d + 2, "canb": 6 * d + 2, "eucl": 3 * d + 3, "cos": 3 * d + 4}[metric]
+    ach = per * pairs / kern_s / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK["fp32_vec_tflops"], "unit": "TFLOP/s",
+            "frac": ach / PEAK["fp32_vec_tflops"], "work": f"{per} flops per pair"}
 
 
 def cpu_baseline(X, L, k, metric, t, seed, n_rows=2048):
@@ -66,24 +108,64 @@ def cpu_baseline(X, L, k, metric, t, seed, n_rows=2048):
         "cores": 1,
         "kind": "oracle",
         "sample": f"Phase 1 on all n={n} rows ({t1 - t0:.1f} s) + Phase 2 on {n_rows} seeded rows "
-                  f"({t2 - t1:.1f} s), Phase 2 extrapolated x{n / n_rows:.0f}; single-threaded NumPy "
-                  f"float64 (host has {os.cpu_count()} cores)",
+                  f"({t2 - t1:.1f} s), Phase 2 time scaled by n/{n_rows}; NumPy float64, one thread "
+                  f"(host reports {os.cpu_count()} cores)",
     }
+
+
+def run_steps(native, Xd, Ld, k, metric, prec, t, seed, steps, warmup, out_a, out_b, out_s):
+    """Warm-up, then `steps` timed requests; per-kernel event times."""
+    import torch
+    stats = {}
+    info = {}
+
+    def step(prof):
+        ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, "pps", t=t, delta=0.01, seed=seed)
+        if prof:
+            native.silh_prof_enable(ctx, True)
+        S, _ = native.silh_pps_sample(ctx)
+        res = native.silh_scores(ctx, a=True, b=True, s=True, mean=True)
+        if prof:
+            for name, (cnt, ms) in native.silh_prof_get(ctx).items():
+                c0, m0 = stats.get(name, (0, 0.0))
+                stats[name] = (c0 + cnt, m0 + ms)
+        if "f0_offsets" not in info:
+            info.update(native.silh_sample_view(ctx))
+        native.silh_destroy(ctx)
+        return S, res["mean"]
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    times = []
+    t_all0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        S, mean = step(True)
+        times.append(time.perf_counter() - ts)
+        print(f"# {metric}/{prec} step {i}: {times[-1] * 1e3:.3f} ms S={S} mean={mean:.7f}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all0
+    return {"S": S, "mean": mean, "t_all": t_all, "times": times, "stats": stats, "info": info}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--metric", default="eucl")
-    ap.add_argument("--prec", default="fp32")
-    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--prec", default="bf16")
+    ap.add_argument("--compare-steps", type=int, default=5,
+                    help="steps of the float32 comparison run and of the Manhattan run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 256 MiB once first (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU row "
-              "sharding is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU row "
+              "sharding of the path is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -91,87 +173,83 @@ def main():
 
     from paper_2607_01993_amd import native, synth
 
-    n, d, k, t, seed = args.n, 32, 16, 256, 1
-    X, L = synth.config_zipf_gauss(n=n, d=d, k=k)
+    n, d, k, t, seed = (WORKLOAD[x] for x in ("n", "d", "k", "t", "seed"))
+    X, L = synth.config_zipf_gauss(n=n, d=d, k=k, seed=seed)
     Xd = torch.from_numpy(X).cuda()
     Ld = torch.from_numpy(L).cuda()
     a = torch.empty(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     s = torch.empty_like(a)
     native.load_library()
-    print(f"# workload ready: n={n} d={d} k={k} t={t} metric={args.metric} prec={args.prec}",
-          file=sys.stderr, flush=True)
-
-    stats = {}
-
-    def step(prof: bool):
-        ctx = native.silh_sample_init(Xd, Ld, k, args.metric, args.prec, "pps", t=t, delta=0.01, seed=seed)
-        if prof:
-            native.silh_prof_enable(ctx, True)
-        S, per = native.silh_pps_sample(ctx)
-        res = native.silh_scores(ctx, a=True, b=True, s=True, mean=True)
-        if prof:
-            for name, (cnt, ms) in native.silh_prof_get(ctx).items():
-                c0, m0 = stats.get(name, (0, 0.0))
-                stats[name] = (c0 + cnt, m0 + ms)
-        view = native.silh_sample_view(ctx) if not stats.get("_view") else None
-        if view is not None:
-            stats["_view"] = view
-        native.silh_destroy(ctx)
-        return S, res["mean"]
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    times = []
-    t_all0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        S, mean = step(True)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        print(f"# step {i}: {times[-1] * 1e3:.2f} ms S={S} mean={mean:.6f}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t_all0
+        print("# copy calibration: 268435456 bytes read, 268435456 bytes written", file=sys.stderr)
+        del src, dst
+    print(f"# workload ready: n={n} d={d} k={k} t={t}", file=sys.stderr, flush=True)
 
-    view = stats.pop("_view")
+    main_run = run_steps(native, Xd, Ld, k, args.metric, args.prec, t, seed, args.steps, args.warmup,
+                         a, b, s)
+    S = main_run["S"]
     sizes = np.bincount(L, minlength=k)
-    f0 = np.diff(view["f0_offsets"])
+    f0 = np.diff(main_run["info"]["f0_offsets"])
     p1 = int((sizes * f0).sum())
     work = n * S + p1
-    ms_step = t_all / args.steps * 1e3
-    value = work / (t_all / args.steps)
+    t_step = main_run["t_all"] / args.steps
+    stats = main_run["stats"]
     p2_cnt, p2_ms = stats.get("phase2", (0, 0.0))
-    p2_avg_s = p2_ms / max(p2_cnt, 1) / 1e3
-    fl = flops_per_pair(args.metric, args.prec, d) * n * S
-    peak = PEAK["fp32_vec_tflops"]
-    roofline = {"bound": "alu", "achieved": fl / p2_avg_s / 1e12, "peak": peak,
-                "unit": "TFLOP/s", "frac": fl / p2_avg_s / 1e12 / peak, "traffic": None,
-                "kernel": "phase2", "kernel_ms": p2_avg_s * 1e3,
-                "flops_per_launch": fl}
-    kernel_ms = {name: round(ms / max(cnt, 1), 4) for name, (cnt, ms) in sorted(stats.items()) if cnt}
+    p2_s = p2_ms / max(p2_cnt, 1) / 1e3
+    roof = phase2_roofline(args.metric, args.prec, d, n, S, p2_s)
+    roof.update({"traffic": traffic_for(args.metric, args.prec), "kernel": "k_p2_mfma" if args.prec in ("bf16", "fp32") and
+                 args.metric in ("eucl", "cos") else "k_p2_valu", "kernel_ms": p2_s * 1e3})
+
+    compare = {}
+    if args.compare_steps > 0 and args.metric == "eucl":
+        ref_prec = "fp32" if args.prec != "fp32" else "bf16"
+        r = run_steps(native, Xd, Ld, k, "eucl", ref_prec, t, seed, args.compare_steps, 1, a, b, s)
+        c2, m2 = r["stats"].get("phase2", (0, 0.0))
+        compare[f"eucl_{ref_prec}"] = {
+            "value": work / (r["t_all"] / args.compare_steps), "ms_per_step": r["t_all"] / args.compare_steps * 1e3,
+            "phase2_ms": m2 / max(c2, 1), "s_mean": r["mean"],
+            "abs_delta_s_mean": abs(r["mean"] - main_run["mean"])}
+        r = run_steps(native, Xd, Ld, k, "manh", "fp32", t, seed, args.compare_steps, 1, a, b, s)
+        c2, m2 = r["stats"].get("phase2", (0, 0.0))
+        sz = np.diff(r["info"]["f0_offsets"])
+        w2 = n * r["S"] + int((sizes * sz).sum())
+        compare["manh_fp32"] = {
+            "value": w2 / (r["t_all"] / args.compare_steps), "ms_per_step": r["t_all"] / args.compare_steps * 1e3,
+            "phase2_ms": m2 / max(c2, 1),
+            "phase2_roofline": phase2_roofline("manh", "fp32", d, n, r["S"], m2 / max(c2, 1) / 1e3)}
+
+    times_ms = np.array(main_run["times"]) * 1e3
     out = {
         "metric": "weighted dist evals/s",
-        "value": value,
+        "value": work / t_step,
         "unit": "weighted dist evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "p50_ms": float(np.percentile(np.array(times) * 1e3, 50)),
-        "p99_ms": float(np.percentile(np.array(times) * 1e3, 99)),
+        "ms_per_step": t_step * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "fp32_valu": "f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"zipf-gauss-blobs n={n} d={d} k={k} t={t} metric={args.metric} "
-                               f"prec={args.prec} sampler=pps delta=0.01",
-                   "n": n, "d": d, "k": k, "t": t, "S": S, "phase1_dists": p1},
-        "phase2_pairs_per_s": n * S / p2_avg_s,
-        "kernel_avg_ms": kernel_ms,
-        "roofline": roofline,
-        "s_mean": mean,
+                               f"prec={args.prec} sampler=pps delta=0.01 seed={seed}",
+                   "n": n, "d": d, "k": k, "t": t, "S": S, "phase1_dists": p1,
+                   "parallelism": "single GPU"},
+        "request_latency_ms": {"p50": float(np.percentile(times_ms, 50)),
+                               "p99": float(np.percentile(times_ms, 99)),
+                               "note": "one request = one whole step, issued back to back"},
+        "phase2_pairs_per_s": n * S / p2_s,
+        "kernel_avg_ms": {name: round(ms / max(cnt, 1), 4) for name, (cnt, ms) in sorted(stats.items())
+                          if cnt},
+        "roofline": roof,
+        "s_mean": main_run["mean"],
+        "compare": compare,
     }
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -256,17 +256,26 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
     sel = uniform53(seed, (uint64_t)g, kStreamUNI) < p ? 1 : 0;
   } else {
     double gam = 1.0 / (double)m;
-    const int fb = f0_off[j], fe = f0_off[j + 1];
     float x[DM];
     const double nx2 = load_row<M, DM>(X, d, g, x);
-    for (int e = fb; e < fe; ++e) {
-      const double w = W[e];
-      const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)e * DM);
-      if (w > 0.0) {
-        const double r = dv / w;
-        gam = r > gam ? r : gam;
+    // Most waves lie inside one cluster (sorted order): then the initial
+    // sample rows and weights are wave-uniform and come in by scalar loads.
+    const int jf = __builtin_amdgcn_readfirstlane(j);
+    auto scan_f0 = [&](int jj) {
+      const int fb = f0_off[jj], fe = f0_off[jj + 1];
+      for (int e = fb; e < fe; ++e) {
+        const double w = W[e];
+        const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)e * DM);
+        if (w > 0.0) {
+          const double r = dv / w;
+          gam = r > gam ? r : gam;
+        }
       }
-    }
+    };
+    if (__all(j == jf))
+      scan_f0(jf);
+    else
+      scan_f0(j);
     p = (double)t * gam;
     p = p < 1.0 ? p : 1.0;
     sel = uniform53(seed, (uint64_t)g, kStreamPPS) < p ? 1 : 0;

@@ -37,6 +37,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
+
 constexpr int kCenterRows = 256;
 
 __host__ __device__ constexpr int round_up_c(int a, int b) { return (a + b - 1) / b * b; }
@@ -259,7 +260,7 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
   gj = gid_pk[row0 + col];
 }
 
-template <int M, int P, int DM>
+template <int M, int P, int DM, int PB>
 __global__ __launch_bounds__(256) void k_p2_mfma(
     const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
@@ -275,78 +276,87 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int col = lane & 31;
-  const int P0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * 32);
+  // PB blocks of 32 elements per wave share every B tile
+  const int P0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 * PB);
+  const float alpha = M == kCos ? 0.5f : 1.0f;
+  const int lane_off = col * C::KP + h * C::HALF;
+  // the element whose sums this lane ends up holding (twice: lanes l, l^1)
+  const int rr = (lane >> 1) & 15;
+  const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
 
-  // this lane's half of its A row (raw or unit-scaled), zero outside [0, d)
-  const int pa = P0 + col < n ? P0 + col : n - 1;
-  float xr[C::HALF];
-  {
+  // this lane's half of its A rows (raw or unit-scaled), zero outside [0, d)
+  float xr[PB][C::HALF];
+  float ux[PB];
+  int pout[PB], own[PB];
+  double w_own[PB], bmin[PB];
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int pb = P0 + 32 * b + col;
+    const int pa = pb < n ? pb : n - 1;
     const float* xp = X + (size_t)pa * d;
 #pragma unroll
     for (int i = 0; i < C::HALF; ++i) {
       const int c = h * C::HALF + i;
-      xr[i] = (c < DM && c < d) ? xp[c] : 0.0f;
+      xr[b][i] = (c < DM && c < d) ? xp[c] : 0.0f;
     }
-  }
-  float ux = 0.f;
-  if (M == kCos) {
-    float p = 0.f;
+    ux[b] = 0.f;
+    if (M == kCos) {
+      float p = 0.f;
 #pragma unroll
-    for (int i = 0; i < C::HALF; ++i) p = fmaf(xr[i], xr[i], p);
-    const float s2 = p + __shfl_xor(p, 32, kWave);
-    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
-    ux = s2 > 0.f ? 0.f : 0.5f;
+      for (int i = 0; i < C::HALF; ++i) p = fmaf(xr[b][i], xr[b][i], p);
+      const float s2 = p + __shfl_xor(p, 32, kWave);
+      const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+      ux[b] = s2 > 0.f ? 0.f : 0.5f;
 #pragma unroll
-    for (int i = 0; i < C::HALF; ++i) xr[i] *= rx;
+      for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
+    }
+    pout[b] = P0 + 32 * b + prow;
+    own[b] = labels[pout[b] < n ? pout[b] : n - 1];
+    w_own[b] = 0.0;
+    bmin[b] = __builtin_inf();
   }
-  const float alpha = M == kCos ? 0.5f : 1.0f;
-  const int lane_off = col * C::KP + h * C::HALF;
 
-  // the element whose sums this lane ends up holding (twice: lanes l, l^1)
-  const int rr = (lane >> 1) & 15;
-  const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
-  const int pout = P0 + prow;
-  const bool pvalid = pout < n;
-  const int own = labels[pvalid ? pout : n - 1];
-
-  double w_own = 0.0;
-  double bmin = __builtin_inf();
-  AFrag<P, DM> A;
-
+  AFrag<P, DM> A[PB];
   for (int j = 0; j < k; ++j) {
-    // ---- A operand for cluster j: x~ = x - mu_j (mu zero-padded to KP),
+    // ---- A operands for cluster j: x~ = x - mu_j (mu zero-padded to KP),
     // rounded to the input precision, plus the augmentation
     {
       const float* m = mu + (size_t)j * C::KP + h * C::HALF;
-      float xq[C::HALF];
-      float part = 0.f;
+      float mv[C::HALF];
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) {
-        float v = xr[i] - m[i];
-        if (P == 1) v = q_bf16(v);
-        xq[i] = v;
-        part = fmaf(v, v, part);
-      }
-      const float nx = part + __shfl_xor(part, 32, kWave);
-      const float an = fmaf(alpha, nx, ux);
-      float aug[C::AUG];
-      if (P == 0) {
-        aug[0] = an;
-        aug[1] = 1.0f;
-      } else {
-        split3(an, aug[0], aug[1], aug[2]);
-        aug[3] = aug[4] = aug[5] = 1.0f;
-      }
+      for (int i = 0; i < C::HALF; ++i) mv[i] = m[i];
 #pragma unroll
-      for (int q = 0; q < C::AUG; ++q) xq[AUG0 + q] = h ? aug[q] : xq[AUG0 + q];
-      if constexpr (P == 0) {
+      for (int b = 0; b < PB; ++b) {
+        float xq[C::HALF];
+        float part = 0.f;
 #pragma unroll
-        for (int s = 0; s < C::NSTEP; ++s) A.v[s] = xq[s];
-      } else {
+        for (int i = 0; i < C::HALF; ++i) {
+          float v = xr[b][i] - mv[i];
+          if (P == 1) v = q_bf16(v);
+          xq[i] = v;
+          part = fmaf(v, v, part);
+        }
+        const float nx = part + __shfl_xor(part, 32, kWave);
+        const float an = fmaf(alpha, nx, ux[b]);
+        float aug[C::AUG];
+        if (P == 0) {
+          aug[0] = an;
+          aug[1] = 1.0f;
+        } else {
+          split3(an, aug[0], aug[1], aug[2]);
+          aug[3] = aug[4] = aug[5] = 1.0f;
+        }
 #pragma unroll
-        for (int s = 0; s < C::NSTEP; ++s)
+        for (int q = 0; q < C::AUG; ++q) xq[AUG0 + q] = h ? aug[q] : xq[AUG0 + q];
+        if constexpr (P == 0) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) A.v[s][e] = (__bf16)xq[8 * s + e];
+          for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
+        } else {
+#pragma unroll
+          for (int s = 0; s < C::NSTEP; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)xq[8 * s + e];
+        }
       }
     }
 
@@ -354,52 +364,63 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     // next tile's loads are issued before this tile's MFMAs)
     const int base = sp_off[j];
     const int ntile = (cnt[j] + 31) >> 5;
-    double wsum = 0.0;
-    float acc[16];
+    double wsum[PB];
+    float acc[PB][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int b = 0; b < PB; ++b) {
+      wsum[b] = 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+    }
     int g = 0;
     auto tile = [&](const BFrag<P, DM>& bf, float wj, int gj, bool last) {
-      f32x16 c;
-      if constexpr (P == 0) {
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[0], bf.v[0].x, f32x16{}, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[1], bf.v[0].y, c, 0, 0, 0);
 #pragma unroll
-        for (int s2 = 1; s2 < C::NSTEP / 2; ++s2) {
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2], bf.v[s2].x, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.v[2 * s2 + 1], bf.v[s2].y, c, 0, 0, 0);
+      for (int b = 0; b < PB; ++b) {
+        f32x16 c;
+        if constexpr (P == 0) {
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[0], bf.v[0].x, f32x16{}, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[1], bf.v[0].y, c, 0, 0, 0);
+#pragma unroll
+          for (int s2 = 1; s2 < C::NSTEP / 2; ++s2) {
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2], bf.v[s2].x, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2 + 1], bf.v[s2].y, c, 0, 0, 0);
+          }
+        } else {
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[0], bf.v[0], f32x16{}, 0, 0, 0);
+#pragma unroll
+          for (int s = 1; s < C::NSTEP; ++s)
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[s], bf.v[s], c, 0, 0, 0);
         }
-      } else {
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v[0], bf.v[0], f32x16{}, 0, 0, 0);
+        if (M == kEucl) {
+          // d(e, e) = 0 exactly: the expanded form leaves rounding noise
+          // there, which the square root would amplify.  Only a column that
+          // holds one of this block's own 32 elements (in this lane's half)
+          // is touched.
+          const int self = gj - (P0 + 32 * b);
+          if ((unsigned)self < 32u && ((self >> 2) & 1) == h) {
+            const int rh = ((self >> 3) << 2) | (self & 3);
 #pragma unroll
-        for (int s = 1; s < C::NSTEP; ++s)
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v[s], bf.v[s], c, 0, 0, 0);
-      }
-      if (M == kEucl) {
-        // d(e, e) = 0 exactly: the expanded form leaves rounding noise there,
-        // which the square root would amplify.  Only a column holding one of
-        // this wave's own 32 elements (in this lane's half) is touched.
-        const int self = gj - P0;
-        if ((unsigned)self < 32u && ((self >> 2) & 1) == h) {
-          const int rh = ((self >> 3) << 2) | (self & 3);
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            if (r == rh) c[r] = 0.0f;
+            for (int r = 0; r < 16; ++r)
+              if (r == rh) c[r] = 0.0f;
+          }
         }
-      }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        float dv;
-        if (M == kEucl)
-          dv = __builtin_amdgcn_sqrtf(fabsf(c[r]));
-        else
-          dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, 2.0f);
-        acc[r] = fmaf(wj, dv, acc[r]);
+        for (int r = 0; r < 16; ++r) {
+          float dv;
+          if (M == kEucl)
+            dv = __builtin_amdgcn_sqrtf(fabsf(c[r]));
+          else
+            dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, 2.0f);
+          acc[b][r] = fmaf(wj, dv, acc[b][r]);
+        }
       }
       if (++g == kFold || last) {
-        wsum += (double)transpose_reduce16(acc, lane);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+        for (int b = 0; b < PB; ++b) {
+          wsum[b] += (double)transpose_reduce16(acc[b], lane);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+        }
         g = 0;
       }
     };
@@ -415,34 +436,52 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         tile(b1, w1, g1, t + 2 == ntile);
       }
     }
-    if (What != nullptr && pvalid && (lane & 1) == 0) What[(size_t)pout * k + j] = (float)wsum;
     const int sz = csize[j];
-    if (j == own) {
-      w_own = wsum;
-    } else if (sz > 0) {
-      const double bj = wsum / (double)sz;
-      bmin = bj < bmin ? bj : bmin;
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      if (What != nullptr && pout[b] < n && (lane & 1) == 0) What[(size_t)pout[b] * k + j] = (float)wsum[b];
+      if (j == own[b]) {
+        w_own[b] = wsum[b];
+      } else if (sz > 0) {
+        const double bj = wsum[b] / (double)sz;
+        bmin[b] = bj < bmin[b] ? bj : bmin[b];
+      }
     }
   }
-  const int szo = csize[own];
-  const double a = szo > 1 ? w_own / (double)(szo - 1) : 0.0;
-  const double b = bmin;
-  const double mx = a > b ? a : b;
-  const double s = (szo > 1 && mx > 0.0) ? (b - a) / mx : 0.0;
-  const bool writer = pvalid && (lane & 1) == 0;
-  if (writer) {
-    if (a_out) a_out[pout] = (float)a;
-    if (b_out) b_out[pout] = (float)b;
-    if (s_out) s_out[pout] = (float)s;
+  double ssum = 0.0;
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int szo = csize[own[b]];
+    const double a = szo > 1 ? w_own[b] / (double)(szo - 1) : 0.0;
+    const double bb = bmin[b];
+    const double mx = a > bb ? a : bb;
+    const double s = (szo > 1 && mx > 0.0) ? (bb - a) / mx : 0.0;
+    const bool writer = pout[b] < n && (lane & 1) == 0;
+    if (writer) {
+      if (a_out) a_out[pout[b]] = (float)a;
+      if (b_out) b_out[pout[b]] = (float)bb;
+      if (s_out) s_out[pout[b]] = (float)s;
+      ssum += s;
+    }
   }
-  const double tot = block_sum_f64<256>(writer ? s : 0.0, sh);
+  const double tot = block_sum_f64<256>(ssum, sh);
   if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
+}
+
+// elements per block of the MFMA kernel (4 waves x 32 x PB)
+// float32 is bound by the MFMA rate: two blocks per wave halve the B-operand
+// traffic per pair.  bf16 keeps one block (four waves per SIMD hide latency
+// better than the second block saves).
+template <int P, int DM>
+constexpr int mfma_pb() {
+  return (P == 0 && DM <= 32) ? 2 : 1;
 }
 
 template <int M, int P, int DM>
 static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym) {
-  const int blocks = (int)ceil_div(A.n, 128);
-  hipLaunchKernelGGL((k_p2_mfma<M, P, DM>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
+  constexpr int PB = mfma_pb<P, DM>();
+  const int blocks = (int)ceil_div(A.n, 128 * PB);
+  hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
                      A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart);
 }
 
@@ -500,6 +539,10 @@ bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float*
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
                         const void* Ym) {
   SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym);
+}
+
+int phase2_mfma_rows(int prec, int DM) {
+  return 128 * ((prec == 0 && DM <= 32) ? 2 : 1);
 }
 
 }  // namespace silh

@@ -338,7 +338,7 @@ silh_status create(const silh_params* prm, const float* X, const int32_t* labels
   c->DM = phase2_valu_dm(prm->d);
   c->mfma = (prm->metric == SILH_EUCL || prm->metric == SILH_COS) &&
             (prm->prec == SILH_FP32 || prm->prec == SILH_BF16);
-  c->p2_rows = c->mfma ? 128 : kP2Rows;
+  c->p2_rows = c->mfma ? phase2_mfma_rows(prm->prec == SILH_BF16 ? 1 : 0, c->DM) : kP2Rows;
   silh_status s = build_index(c);
   if (s != SILH_OK) {
     std::string msg = g_err;

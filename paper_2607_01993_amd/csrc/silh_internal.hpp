@@ -88,7 +88,8 @@ void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
                       void* Ym);
-// one block of 256 threads per 128 elements
+// elements per 256-thread block of the MFMA Phase-2 kernel
+int phase2_mfma_rows(int prec, int DM);
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
                         const void* Ym);
 

@@ -73,6 +73,13 @@ def load_library(path: str = LIB_PATH):
     global _lib
     with _lock:
         if _lib is None:
+            # PyTorch ships its own HIP runtime under the same soname; load it
+            # first so that the library and torch share one runtime (streams and
+            # device memory are exchanged between them)
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             if not os.path.exists(path):
                 raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_01993_amd.build`")
             lib = ctypes.CDLL(path)
