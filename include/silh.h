@@ -56,7 +56,11 @@ typedef enum { SILH_EUCL = 0, SILH_COS = 1, SILH_MANH = 2, SILH_CANB = 3 } silh_
  *                  vector ALUs.
  *  SILH_BF16       bf16 operands, float32 accumulation (v_mfma_f32_32x32x16_bf16);
  *                  Euclidean and cosine only.
- *  SILH_FP8        OCP e4m3 operands (reserved; not built yet).
+ *  SILH_FP8        OCP e4m3 operands, float32 accumulation
+ *                  (v_mfma_f32_32x32x64_f8f6f4); cosine with d >= 64 only
+ *                  (the K step is 64 wide, and at smaller d the 3-bit
+ *                  mantissa's error per coordinate no longer averages out).
+ *                  Operands are the centred unit vectors times 64.
  *  SILH_FP32_VALU  float32 on the vector ALUs for every metric. */
 typedef enum { SILH_FP32 = 0, SILH_BF16 = 1, SILH_FP8 = 2, SILH_FP32_VALU = 3 } silh_prec;
 

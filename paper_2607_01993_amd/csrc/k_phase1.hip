@@ -143,24 +143,25 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
   __shared__ double sh[4];
   const int32_t* it = items + (size_t)blockIdx.x * 6;
   const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
+  // one member row per thread (items hold at most 256 members), read once
+  const int r = begin + threadIdx.x;
+  const bool have = r < end;
+  float x[DM];
+  double nx2 = 0.0;
+  if (have) {
+    nx2 = load_row<M, DM>(X, d, perm[r], x);
+  } else {
+#pragma unroll
+    for (int c = 0; c < DM; ++c) x[c] = 0.0f;
+  }
   for (int e0 = 0; e0 < f0n; e0 += kEB) {
     const int ne = f0n - e0 < kEB ? f0n - e0 : kEB;
-    double acc[kEB];
-#pragma unroll
-    for (int e = 0; e < kEB; ++e) acc[e] = 0.0;
-    for (int r = begin + threadIdx.x; r < end; r += 256) {
-      float x[DM];
-      const double nx2 = load_row<M, DM>(X, d, perm[r], x);
-#pragma unroll
-      for (int e = 0; e < kEB; ++e) {
-        const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
-        acc[e] = acc[e] + dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
-      }
-    }
 #pragma unroll
     for (int e = 0; e < kEB; ++e) {
+      const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
+      const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
       if (e < ne) {  // ne is uniform over the block
-        const double tot = block_sum_f64<256>(acc[e], sh);
+        const double tot = block_sum_f64<256>(have ? dv : 0.0, sh);
         if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
       }
     }

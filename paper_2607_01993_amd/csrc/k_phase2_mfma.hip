@@ -35,6 +35,12 @@ namespace silh {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// fp8 (OCP e4m3) path, cosine only: operands are 64 (x~ - y~ components of
+// unit vectors lie in [-2, 2], so |64 v| <= 128 < 448) times the centred
+// coordinates; the squared norms enter through the accumulator input.
+constexpr float kFp8Scale = 64.0f;
 
 constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
 
@@ -42,17 +48,28 @@ constexpr int kCenterRows = 256;
 
 __host__ __device__ constexpr int round_up_c(int a, int b) { return (a + b - 1) / b * b; }
 
+// P = 0: float32 operands (32x32x2), P = 1: bf16 (32x32x16), P = 2: fp8 (32x32x64)
 template <int P, int DM>
 struct MCfg {
-  static constexpr int AUG = P == 0 ? 2 : 6;
-  static constexpr int KP = P == 0 ? round_up_c(DM + AUG, 4) : round_up_c(DM + AUG, 16);
+  static constexpr int AUG = P == 0 ? 2 : (P == 1 ? 6 : 0);
+  static constexpr int KP = P == 0 ? round_up_c(DM + AUG, 4)
+                                   : (P == 1 ? round_up_c(DM + AUG, 16) : round_up_c(DM, 64));
   static constexpr int HALF = KP / 2;
-  static constexpr int NSTEP = P == 0 ? HALF : HALF / 8;
+  static constexpr int NSTEP = P == 0 ? HALF : (P == 1 ? HALF / 8 : HALF / 32);
 };
 
 int mfma_kp(int prec, int DM) {
   if (prec == 0) return round_up_c(DM + 2, 4);
-  return round_up_c(DM + 6, 16);
+  if (prec == 1) return round_up_c(DM + 6, 16);
+  return round_up_c(DM, 64);
+}
+
+__device__ __forceinline__ int fp8_pack4(float a, float b, float c, float d) {
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+}
+__device__ __forceinline__ float q_fp8(float v) {
+  return __builtin_amdgcn_cvt_f32_fp8(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false), 0);
 }
 
 __device__ __forceinline__ float q_bf16(float v) { return (float)(__bf16)v; }
@@ -113,7 +130,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
                                                    const int32_t* __restrict__ sp_off,
                                                    const int32_t* __restrict__ cnt, int k,
                                                    const float* __restrict__ mu, int S_pad,
-                                                   void* __restrict__ Ym) {
+                                                   void* __restrict__ Ym, float* __restrict__ bnorm) {
   using C = MCfg<P, DM>;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S_pad) return;
@@ -129,6 +146,28 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
   float row[C::KP];
 #pragma unroll
   for (int c = 0; c < C::KP; ++c) row[c] = 0.f;
+  if (P == 2) {
+    // fp8: B = e4m3(-64 y~), the norm term alpha |y~_q|^2 + u_y goes to bnorm
+    float bn = 0.0f;
+    if (real) {
+      const float* y = Y32 + (size_t)s * DM;
+      const float* m = mu + (size_t)j * C::KP;
+      float ny = 0.f;
+#pragma unroll
+      for (int c = 0; c < DM; ++c) {
+        const float q = q_fp8(kFp8Scale * (y[c] - m[c]));
+        const float v = q * (1.0f / kFp8Scale);
+        ny = fmaf(v, v, ny);
+        row[c] = -q;
+      }
+      bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
+    }
+    bnorm[s] = bn;
+    int* out = (int*)((unsigned char*)Ym + (size_t)s * C::KP);
+#pragma unroll
+    for (int c = 0; c < C::KP; c += 4) out[c / 4] = fp8_pack4(row[c], row[c + 1], row[c + 2], row[c + 3]);
+    return;
+  }
   if (real) {
     const float* y = Y32 + (size_t)s * DM;
     const float* m = mu + (size_t)j * C::KP;
@@ -149,7 +188,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       split3(bn, row[DM + 3], row[DM + 4], row[DM + 5]);
     }
   }
-  if (P == 0) {
+  if constexpr (P == 0) {
     float* out = (float*)Ym + (size_t)s * C::KP;
 #pragma unroll
     for (int c = 0; c < C::KP; ++c) out[c] = row[c];
@@ -229,6 +268,10 @@ template <int DM>
 struct AFrag<1, DM> {
   bf16x8 v[MCfg<1, DM>::NSTEP];
 };
+template <int DM>
+struct AFrag<2, DM> {
+  i32x8 v[MCfg<2, DM>::NSTEP];
+};
 
 template <int P, int DM>
 struct BFrag;
@@ -240,14 +283,30 @@ template <int DM>
 struct BFrag<1, DM> {
   bf16x8 v[MCfg<1, DM>::NSTEP];
 };
+template <int DM>
+struct BFrag<2, DM> {
+  i32x8 v[MCfg<2, DM>::NSTEP];
+};
 
-// one tile's B operand (this lane's half row), weight and element id
+// one tile's B operand (this lane's half row), weight and element id (the
+// fp8 path loads the sample's norm term instead of the id)
 template <int P, int DM>
 __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const float* __restrict__ w,
-                                          const int32_t* __restrict__ gid_pk, int row0, int lane_off,
+                                          const int32_t* __restrict__ gid_pk,
+                                          const float* __restrict__ bnorm, int row0, int lane_off,
                                           int col, BFrag<P, DM>& b, float& wj, int& gj) {
   using C = MCfg<P, DM>;
-  if constexpr (P == 0) {
+  if constexpr (P == 2) {
+    const uint4* bp = (const uint4*)((const unsigned char*)Ym + (size_t)row0 * C::KP + lane_off);
+#pragma unroll
+    for (int s = 0; s < C::NSTEP; ++s) {
+      const uint4 lo = bp[2 * s], hi = bp[2 * s + 1];
+      b.v[s] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+    wj = w[row0 + col];
+    gj = __float_as_int(bnorm[row0 + col]);
+    return;
+  } else if constexpr (P == 0) {
     const float2* bp = (const float2*)((const float*)Ym + (size_t)row0 * C::KP + lane_off);
 #pragma unroll
     for (int s2 = 0; s2 < C::NSTEP / 2; ++s2) b.v[s2] = bp[s2];
@@ -267,11 +326,12 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt,
     const int32_t* __restrict__ csize, int k, const float* __restrict__ mu,
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
-    float* __restrict__ What, double* __restrict__ bpart) {
+    float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm) {
   using C = MCfg<P, DM>;
   // the augmentation columns always fall in the upper half of the row
   constexpr int AUG0 = DM - C::HALF;
-  static_assert(AUG0 >= 0 && AUG0 + C::AUG <= C::HALF, "augmentation placement");
+  static_assert(C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
+  constexpr float S2 = kFp8Scale * kFp8Scale;
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
@@ -284,9 +344,11 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   const int rr = (lane >> 1) & 15;
   const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
 
-  // this lane's half of its A rows (raw or unit-scaled), zero outside [0, d)
+  // this lane's half of its A rows (raw or unit-scaled), zero outside [0, d).
+  // Long rows are not kept: they are re-read per cluster (L2) and rescaled.
+  constexpr bool kKeepX = C::HALF <= 40;
   float xr[PB][C::HALF];
-  float ux[PB];
+  float ux[PB], rxs[PB];
   int pout[PB], own[PB];
   double w_own[PB], bmin[PB];
 #pragma unroll
@@ -300,6 +362,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       xr[b][i] = (c < DM && c < d) ? xp[c] : 0.0f;
     }
     ux[b] = 0.f;
+    rxs[b] = 1.f;
     if (M == kCos) {
       float p = 0.f;
 #pragma unroll
@@ -307,6 +370,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       const float s2 = p + __shfl_xor(p, 32, kWave);
       const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
       ux[b] = s2 > 0.f ? 0.f : 0.5f;
+      rxs[b] = rx;
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
     }
@@ -317,10 +381,11 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   }
 
   AFrag<P, DM> A[PB];
+  float nxc[P == 2 ? PB : 1][16];   // fp8: 64^2 (alpha |x~_q|^2 + u_x) of the 16 C rows
   for (int j = 0; j < k; ++j) {
     // ---- A operands for cluster j: x~ = x - mu_j (mu zero-padded to KP),
     // rounded to the input precision, plus the augmentation
-    {
+    if constexpr (kKeepX) {
       const float* m = mu + (size_t)j * C::KP + h * C::HALF;
       float mv[C::HALF];
 #pragma unroll
@@ -329,6 +394,26 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       for (int b = 0; b < PB; ++b) {
         float xq[C::HALF];
         float part = 0.f;
+        if constexpr (P == 2) {
+#pragma unroll
+          for (int i = 0; i < C::HALF; ++i) {
+            const float q = q_fp8(kFp8Scale * (xr[b][i] - mv[i]));
+            const float v = q * (1.0f / kFp8Scale);
+            xq[i] = q;
+            part = fmaf(v, v, part);
+          }
+          const float rowv = S2 * fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
+          // the C rows of this lane are elements 8(r/4) + 4h + r%4 of the block
+#pragma unroll
+          for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
+#pragma unroll
+          for (int s = 0; s < C::NSTEP; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              A[b].v[s][e] = fp8_pack4(xq[32 * s + 4 * e], xq[32 * s + 4 * e + 1], xq[32 * s + 4 * e + 2],
+                                       xq[32 * s + 4 * e + 3]);
+          continue;
+        }
 #pragma unroll
         for (int i = 0; i < C::HALF; ++i) {
           float v = xr[b][i] - mv[i];
@@ -338,11 +423,11 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         }
         const float nx = part + __shfl_xor(part, 32, kWave);
         const float an = fmaf(alpha, nx, ux[b]);
-        float aug[C::AUG];
-        if (P == 0) {
+        float aug[C::AUG > 0 ? C::AUG : 1];
+        if constexpr (P == 0) {
           aug[0] = an;
           aug[1] = 1.0f;
-        } else {
+        } else if constexpr (P == 1) {
           split3(an, aug[0], aug[1], aug[2]);
           aug[3] = aug[4] = aug[5] = 1.0f;
         }
@@ -351,11 +436,78 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         if constexpr (P == 0) {
 #pragma unroll
           for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
-        } else {
+        } else if constexpr (P == 1) {
 #pragma unroll
           for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
             for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)xq[8 * s + e];
+        }
+      }
+    } else {
+      // long rows: built step by step from the row (re-read) and the centre
+      const float* m = mu + (size_t)j * C::KP + h * C::HALF;
+      constexpr int E = P == 0 ? 1 : (P == 1 ? 8 : 32);   // elements per MFMA step
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        const int pb = P0 + 32 * b + col;
+        const float* xp = X + (size_t)(pb < n ? pb : n - 1) * d;
+        float part = 0.f;
+#pragma unroll
+        for (int s = 0; s < C::NSTEP; ++s) {
+          float q[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = s * E + e;
+            const int c = h * C::HALF + i;
+            const float xv = (c < DM && c < d) ? xp[c] * rxs[b] : 0.0f;
+            float v = xv - m[i];
+            if (P == 2) {
+              v = q_fp8(kFp8Scale * v);
+              const float dq = v * (1.0f / kFp8Scale);
+              part = fmaf(dq, dq, part);
+            } else {
+              if (P == 1) v = q_bf16(v);
+              part = fmaf(v, v, part);
+            }
+            q[e] = v;
+          }
+          if constexpr (P == 0) {
+            A[b].v[s] = q[0];
+          } else if constexpr (P == 1) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)q[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) A[b].v[s][e] = fp8_pack4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
+          }
+        }
+        const float nx = part + __shfl_xor(part, 32, kWave);
+        const float an = fmaf(alpha, nx, ux[b]);
+        if constexpr (P == 2) {
+          const float rowv = S2 * an;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
+        } else {
+          float aug[C::AUG > 0 ? C::AUG : 1];
+          if constexpr (P == 0) {
+            aug[0] = an;
+            aug[1] = 1.0f;
+          } else {
+            split3(an, aug[0], aug[1], aug[2]);
+            aug[3] = aug[4] = aug[5] = 1.0f;
+          }
+#pragma unroll
+          for (int q2 = 0; q2 < C::AUG; ++q2) {
+            constexpr int dummy = 0;
+            (void)dummy;
+            const int i = AUG0 + q2;
+            if constexpr (P == 0) {
+              A[b].v[i] = h ? aug[q2] : A[b].v[i];
+            } else {
+              const __bf16 cur = A[b].v[i / 8][i % 8];
+              A[b].v[i / 8][i % 8] = h ? (__bf16)aug[q2] : cur;
+            }
+          }
         }
       }
     }
@@ -385,11 +537,20 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
             c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2], bf.v[s2].x, c, 0, 0, 0);
             c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2 + 1], bf.v[s2].y, c, 0, 0, 0);
           }
-        } else {
+        } else if constexpr (P == 1) {
           c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[0], bf.v[0], f32x16{}, 0, 0, 0);
 #pragma unroll
           for (int s = 1; s < C::NSTEP; ++s)
             c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[s], bf.v[s], c, 0, 0, 0);
+        } else {
+          // fp8: the accumulator starts at 64^2 (row term + column term), the
+          // MFMA adds -64^2 x~_q . y~_q (unscaled f8f6f4 form, e4m3 operands)
+          const float bcol = S2 * __int_as_float(gj);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) c[r] = nxc[b][r] + bcol;
+#pragma unroll
+          for (int s = 0; s < C::NSTEP; ++s)
+            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], bf.v[s], c, 0, 0, 0, 0, 0, 0);
         }
         if (M == kEucl) {
           // d(e, e) = 0 exactly: the expanded form leaves rounding noise
@@ -404,14 +565,15 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
               if (r == rh) c[r] = 0.0f;
           }
         }
+        const float wt = P == 2 ? wj * (1.0f / S2) : wj;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           float dv;
           if (M == kEucl)
             dv = __builtin_amdgcn_sqrtf(fabsf(c[r]));
           else
-            dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, 2.0f);
-          acc[b][r] = fmaf(wj, dv, acc[b][r]);
+            dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
+          acc[b][r] = fmaf(wt, dv, acc[b][r]);
         }
       }
       if (++g == kFold || last) {
@@ -424,16 +586,27 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         g = 0;
       }
     };
-    BFrag<P, DM> b0, b1;
-    float w0 = 0.f, w1 = 0.f;
-    int g0 = -1, g1 = -1;
-    if (ntile > 0) load_tile<P, DM>(Ym, w, gid_pk, base, lane_off, col, b0, w0, g0);
-    for (int t = 0; t < ntile; t += 2) {
-      if (t + 1 < ntile) load_tile<P, DM>(Ym, w, gid_pk, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
-      tile(b0, w0, g0, t + 1 == ntile);
-      if (t + 1 < ntile) {
-        if (t + 2 < ntile) load_tile<P, DM>(Ym, w, gid_pk, base + (t + 2) * 32, lane_off, col, b0, w0, g0);
-        tile(b1, w1, g1, t + 2 == ntile);
+    if constexpr (C::HALF > 40) {
+      // long rows: one B buffer (registers go to occupancy instead)
+      BFrag<P, DM> b0;
+      float w0 = 0.f;
+      int g0 = -1;
+      for (int t = 0; t < ntile; ++t) {
+        load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + t * 32, lane_off, col, b0, w0, g0);
+        tile(b0, w0, g0, t + 1 == ntile);
+      }
+    } else {
+      BFrag<P, DM> b0, b1;
+      float w0 = 0.f, w1 = 0.f;
+      int g0 = -1, g1 = -1;
+      if (ntile > 0) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
+      for (int t = 0; t < ntile; t += 2) {
+        if (t + 1 < ntile) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
+        tile(b0, w0, g0, t + 1 == ntile);
+        if (t + 1 < ntile) {
+          if (t + 2 < ntile) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 2) * 32, lane_off, col, b0, w0, g0);
+          tile(b1, w1, g1, t + 2 == ntile);
+        }
       }
     }
     const int sz = csize[j];
@@ -478,18 +651,21 @@ constexpr int mfma_pb() {
 }
 
 template <int M, int P, int DM>
-static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym) {
+static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
+                            const float* bnorm) {
   constexpr int PB = mfma_pb<P, DM>();
   const int blocks = (int)ceil_div(A.n, 128 * PB);
   hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
-                     A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart);
+                     A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart,
+                     bnorm);
 }
 
 template <int M, int P, int DM>
 static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, const int32_t* sp_off,
-                            const int32_t* cnt, int k, const float* mu, int S_pad, void* Ym) {
+                            const int32_t* cnt, int k, const float* mu, int S_pad, void* Ym,
+                            float* bnorm) {
   hipLaunchKernelGGL((k_pack_mfma<M, P, DM>), dim3((int)ceil_div(S_pad, 256)), dim3(256), 0, st, Y32,
-                     aux, sp_off, cnt, k, mu, S_pad, Ym);
+                     aux, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
 }
 
 #define SILH_MFMA_DISPATCH(FN, ...)                                     \
@@ -526,19 +702,27 @@ static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, 
         case 64: FN<kCos, 1, 64>(__VA_ARGS__); return true;             \
         case 128: FN<kCos, 1, 128>(__VA_ARGS__); return true;           \
       }                                                                 \
+    } else if (metric == kCos && prec == 2) {                           \
+      switch (DM) {                                                     \
+        case 8: FN<kCos, 2, 8>(__VA_ARGS__); return true;               \
+        case 16: FN<kCos, 2, 16>(__VA_ARGS__); return true;             \
+        case 32: FN<kCos, 2, 32>(__VA_ARGS__); return true;             \
+        case 64: FN<kCos, 2, 64>(__VA_ARGS__); return true;             \
+        case 128: FN<kCos, 2, 128>(__VA_ARGS__); return true;           \
+      }                                                                 \
     }                                                                   \
     return false;                                                       \
   } while (0)
 
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
-                      void* Ym) {
-  SILH_MFMA_DISPATCH(launch_pack_one, st, Y32, aux, sp_off, cnt, k, mu, S_pad, Ym);
+                      void* Ym, float* bnorm) {
+  SILH_MFMA_DISPATCH(launch_pack_one, st, Y32, aux, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
 }
 
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
-                        const void* Ym) {
-  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym);
+                        const void* Ym, const float* bnorm) {
+  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym, bnorm);
 }
 
 int phase2_mfma_rows(int prec, int DM) {

@@ -67,6 +67,7 @@ const char* const kSlotNames[K_NSLOTS] = {
 constexpr int64_t kMaxN = (int64_t)1 << 30;
 constexpr int kMaxK = 4096;
 constexpr int kMaxD = 256;
+constexpr int kFp8MinD = 64;
 
 }  // namespace
 
@@ -78,6 +79,7 @@ struct silh_ctx {
   const int32_t* labels = nullptr;
   int n = 0, d = 0, k = 0, DM = 0;
   bool mfma = false;  // Phase 2 on the matrix cores
+  int mprec = 0;      // MFMA operand type: 0 float32, 1 bf16, 2 fp8
   int p2_rows = kP2Rows;
   int state = 0;  // 0 = indexed, 1 = sampled
 
@@ -109,7 +111,7 @@ struct silh_ctx {
   int64_t *f0_gid = nullptr, *gid_view = nullptr;
   double *f0X = nullptr, *W0 = nullptr, *partial = nullptr, *p_gid = nullptr;
   int32_t *s_off = nullptr, *sp_off = nullptr, *cnt = nullptr, *gid_pk = nullptr;
-  float *w32 = nullptr, *aux32 = nullptr, *Y32 = nullptr, *mu = nullptr;
+  float *w32 = nullptr, *aux32 = nullptr, *Y32 = nullptr, *mu = nullptr, *bnorm = nullptr;
   void* Ym = nullptr;
   double *bpart = nullptr, *mean_d = nullptr;
 
@@ -237,8 +239,10 @@ silh_status check_params(const silh_params* prm, const float* X, const int32_t* 
   if ((prm->alloc == nullptr) != (prm->free == nullptr))
     return fail(SILH_E_ARG, "alloc and free must be given together");
   const bool mfma_metric = prm->metric == SILH_EUCL || prm->metric == SILH_COS;
-  if (prm->prec == SILH_FP8 || (prm->prec == SILH_BF16 && !mfma_metric))
+  if ((prm->prec == SILH_FP8 && prm->metric != SILH_COS) || (prm->prec == SILH_BF16 && !mfma_metric))
     return fail(SILH_E_UNSUPPORTED, "precision %d is not built for metric %d", prm->prec, prm->metric);
+  if (prm->prec == SILH_FP8 && prm->d < kFp8MinD)
+    return fail(SILH_E_UNSUPPORTED, "fp8 operands need d >= %d (d=%d)", kFp8MinD, prm->d);
   if (phase2_valu_dm(prm->d) == 0)
     return fail(SILH_E_UNSUPPORTED, "d=%d has no Phase-2 kernel (d <= 128)", prm->d);
   int64_t t = prm->t;
@@ -337,8 +341,9 @@ silh_status create(const silh_params* prm, const float* X, const int32_t* labels
   c->k = prm->k;
   c->DM = phase2_valu_dm(prm->d);
   c->mfma = (prm->metric == SILH_EUCL || prm->metric == SILH_COS) &&
-            (prm->prec == SILH_FP32 || prm->prec == SILH_BF16);
-  c->p2_rows = c->mfma ? phase2_mfma_rows(prm->prec == SILH_BF16 ? 1 : 0, c->DM) : kP2Rows;
+            (prm->prec == SILH_FP32 || prm->prec == SILH_BF16 || prm->prec == SILH_FP8);
+  c->mprec = prm->prec == SILH_BF16 ? 1 : (prm->prec == SILH_FP8 ? 2 : 0);
+  c->p2_rows = c->mfma ? phase2_mfma_rows(c->mprec, c->DM) : kP2Rows;
   silh_status s = build_index(c);
   if (s != SILH_OK) {
     std::string msg = g_err;
@@ -396,10 +401,11 @@ silh_status compact_and_pack(silh_ctx* c) {
     CHK(L.done());
   }
   if (c->mfma && c->S_pad > 0) {
-    const int prec = c->prm.prec == SILH_BF16 ? 1 : 0;
+    const int prec = c->mprec;
     const int KP = mfma_kp(prec, c->DM);
     CHK(dalloc(c, c->alloc_sample, &c->mu, (size_t)k * KP));
-    void* ym = raw_alloc(c, (size_t)c->S_pad * KP * (prec ? 2 : 4));
+    CHK(dalloc(c, c->alloc_sample, &c->bnorm, (size_t)c->S_pad));
+    void* ym = raw_alloc(c, (size_t)c->S_pad * KP * (prec == 0 ? 4 : (prec == 1 ? 2 : 1)));
     if (!ym) return fail(SILH_E_NOMEM, "device allocation of the packed sample failed");
     c->alloc_sample.push_back(ym);
     c->Ym = ym;
@@ -411,7 +417,7 @@ silh_status compact_and_pack(silh_ctx* c) {
     {
       Launch L(c, K_PACK_MFMA);
       if (!launch_pack_mfma(c->st, c->prm.metric, prec, c->DM, c->Y32, c->aux32, c->sp_off, c->cnt, k,
-                            c->mu, (int)c->S_pad, c->Ym))
+                            c->mu, (int)c->S_pad, c->Ym, c->bnorm))
         return fail(SILH_E_UNSUPPORTED, "no MFMA packing for metric %d, d=%d", c->prm.metric, c->d);
       CHK(L.done());
     }
@@ -542,8 +548,8 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
   A.bpart = c->bpart;
   {
     Launch L(c, K_PHASE2);
-    const bool ok = c->mfma ? launch_phase2_mfma(c->st, c->prm.metric, c->prm.prec == SILH_BF16 ? 1 : 0,
-                                                 c->DM, A, c->mu, c->Ym)
+    const bool ok = c->mfma ? launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym,
+                                                 c->bnorm)
                             : launch_phase2_valu(c->st, c->prm.metric, c->DM, A);
     if (!ok) return fail(SILH_E_UNSUPPORTED, "no Phase-2 kernel for metric %d, d=%d", c->prm.metric, c->d);
     CHK(L.done());

@@ -11,7 +11,7 @@ constexpr int kSortSeg = 1024;
 // Elements per block of the int32 exclusive scan (256 threads x 8).
 constexpr int kScanTile = 2048;
 // Members per work item of the W(e_bar) partial sums.
-constexpr int kWChunk = 512;
+constexpr int kWChunk = 256;   // one member per thread of a 256-thread block
 // Sample rows of each cluster are padded to a multiple of this.
 constexpr int kSamplePad = 32;
 // Rows per Phase-2 block in the VALU kernel.
@@ -80,18 +80,19 @@ struct P2Args {
 bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& a);
 int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if unsupported
 
-// MFMA path (Euclidean, cosine; float32 or bf16 operands)
+// MFMA path (Euclidean and cosine with float32 or bf16 operands; cosine with
+// fp8 operands).  prec: 0 float32, 1 bf16, 2 fp8.
 int mfma_kp(int prec, int DM);   // contraction length of a packed row
 // mu: [k][KP] centres, zero beyond DM
 void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32_t* sp_off,
                    const int32_t* cnt, int k, float* mu);
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
-                      void* Ym);
+                      void* Ym, float* bnorm);
 // elements per 256-thread block of the MFMA Phase-2 kernel
 int phase2_mfma_rows(int prec, int DM);
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
-                        const void* Ym);
+                        const void* Ym, const float* bnorm);
 
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
