@@ -36,6 +36,8 @@ namespace silh {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // fp8 (OCP e4m3) path, cosine only: operands are 64 (x~ - y~ components of
 // unit vectors lie in [-2, 2], so |64 v| <= 128 < 448) times the centred
@@ -56,6 +58,7 @@ struct MCfg {
                                    : (P == 1 ? round_up_c(DM + AUG, 16) : round_up_c(DM, 64));
   static constexpr int HALF = KP / 2;
   static constexpr int NSTEP = P == 0 ? HALF : (P == 1 ? HALF / 8 : HALF / 32);
+  static constexpr int ELEM = P == 0 ? 4 : (P == 1 ? 2 : 1);  // operand bytes
 };
 
 int mfma_kp(int prec, int DM) {
@@ -288,35 +291,45 @@ struct BFrag<2, DM> {
   i32x8 v[MCfg<2, DM>::NSTEP];
 };
 
+// A raw buffer resource over `bytes` bytes at p (gfx9 descriptor: stride 0,
+// offsets are byte offsets, reads past `bytes` return 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+
 // one tile's B operand (this lane's half row), weight and element id (the
 // fp8 path loads the sample's norm term instead of the id)
 template <int P, int DM>
 __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const float* __restrict__ w,
                                           const int32_t* __restrict__ gid_pk,
-                                          const float* __restrict__ bnorm, int row0, int lane_off,
-                                          int col, BFrag<P, DM>& b, float& wj, int& gj) {
+                                          const float* __restrict__ bnorm, int row0, uint32_t lane_off,
+                                          uint32_t col, BFrag<P, DM>& b, float& wj, int& gj) {
   using C = MCfg<P, DM>;
+  // row0 is wave-uniform: each 32-row tile gets buffer descriptors built on
+  // the scalar unit, and a lane reads at a fixed byte offset (no per-tile
+  // vector address arithmetic)
+  const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)row0 * (size_t)(C::KP * C::ELEM),
+                          32 * C::KP * C::ELEM);
+  const auto rw = rsrc_at(w + row0, 32 * 4);
+  const auto rg = rsrc_at(P == 2 ? (const void*)(bnorm + row0) : (const void*)(gid_pk + row0), 32 * 4);
   if constexpr (P == 2) {
-    const uint4* bp = (const uint4*)((const unsigned char*)Ym + (size_t)row0 * C::KP + lane_off);
 #pragma unroll
     for (int s = 0; s < C::NSTEP; ++s) {
-      const uint4 lo = bp[2 * s], hi = bp[2 * s + 1];
+      const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 32u * s, 0, 0);
+      const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 32u * s + 16u, 0, 0);
       b.v[s] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     }
-    wj = w[row0 + col];
-    gj = __float_as_int(bnorm[row0 + col]);
-    return;
   } else if constexpr (P == 0) {
-    const float2* bp = (const float2*)((const float*)Ym + (size_t)row0 * C::KP + lane_off);
 #pragma unroll
-    for (int s2 = 0; s2 < C::NSTEP / 2; ++s2) b.v[s2] = bp[s2];
+    for (int s2 = 0; s2 < C::NSTEP / 2; ++s2)
+      b.v[s2] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rb, lane_off + 8u * s2, 0, 0));
   } else {
-    const bf16x8* bp = (const bf16x8*)((const __bf16*)Ym + (size_t)row0 * C::KP + lane_off);
 #pragma unroll
-    for (int s = 0; s < C::NSTEP; ++s) b.v[s] = bp[s];
+    for (int s = 0; s < C::NSTEP; ++s)
+      b.v[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 16u * s, 0, 0));
   }
-  wj = w[row0 + col];
-  gj = gid_pk[row0 + col];
+  wj = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * col, 0, 0));
+  gj = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0);
 }
 
 template <int M, int P, int DM, int PB>
@@ -339,7 +352,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   // PB blocks of 32 elements per wave share every B tile
   const int P0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 * PB);
   const float alpha = M == kCos ? 0.5f : 1.0f;
-  const int lane_off = col * C::KP + h * C::HALF;
+  const uint32_t lane_off = (uint32_t)((col * C::KP + h * C::HALF) * C::ELEM);  // bytes
   // the element whose sums this lane ends up holding (twice: lanes l, l^1)
   const int rr = (lane >> 1) & 15;
   const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
@@ -596,18 +609,23 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         tile(b0, w0, g0, t + 1 == ntile);
       }
     } else {
+      // Tiles go in pairs with unconditional prefetches (the one past the
+      // cluster's last tile re-reads that tile), so the wait before each
+      // tile covers only that tile's loads; an odd last tile runs after the
+      // loop from the buffer already loaded.
       BFrag<P, DM> b0, b1;
       float w0 = 0.f, w1 = 0.f;
       int g0 = -1, g1 = -1;
       if (ntile > 0) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
-      for (int t = 0; t < ntile; t += 2) {
-        if (t + 1 < ntile) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
-        tile(b0, w0, g0, t + 1 == ntile);
-        if (t + 1 < ntile) {
-          if (t + 2 < ntile) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 2) * 32, lane_off, col, b0, w0, g0);
-          tile(b1, w1, g1, t + 2 == ntile);
-        }
+      int t = 0;
+      for (; t + 2 <= ntile; t += 2) {
+        load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
+        tile(b0, w0, g0, false);
+        const int t2 = t + 2 < ntile ? t + 2 : ntile - 1;
+        load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + t2 * 32, lane_off, col, b0, w0, g0);
+        tile(b1, w1, g1, t + 2 == ntile);
       }
+      if (t < ntile) tile(b0, w0, g0, true);
     }
     const int sz = csize[j];
 #pragma unroll
