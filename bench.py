@@ -28,8 +28,8 @@ if ROOT not in sys.path:
 
 # MI355X figures: published peaks, and unit-count derivations from them
 # (256 CUs at 2.4 GHz).  157.3 TFLOP/s fp32 vector = 128 fp32 lanes / clk / CU
-# doing FMAs; transcendental instructions (v_sqrt_f32) issue at a quarter of
-# that, 32 lanes / clk / CU.
+# doing packed FMAs (64 without packing); transcendental instructions
+# (v_sqrt_f32) run at 32 lanes / clk / CU.
 CU, CLK = 256, 2.4e9
 PEAK = {
     "hbm_gbs": 8000.0,
@@ -45,8 +45,8 @@ WORKLOAD = dict(n=1_000_000, d=32, k=16, t=256, seed=1)
 # runs (FETCH_SIZE, WRITE_SIZE; scaled by a 256 MiB copy), valid only for the
 # kernel source they were taken with (sha256 prefix of the source file).
 TRAFFIC = {
-    ("eucl", "bf16"): {"src": "paper_2607_01993_amd/csrc/k_phase2_mfma.hip", "sha256": "81dc4c04e5e2beb5",
-                       "bytes": (136.2 + 12.3) * 1e6,
+    ("eucl", "bf16"): {"src": "paper_2607_01993_amd/csrc/k_phase2_mfma.hip", "sha256": "53474416cf396e41",
+                       "bytes": (139.1 + 12.3) * 1e6,
                        "profile": "profiles/hbm_traffic_zipf_n1e6_d32_k16_t256.md"},
 }
 
