@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,19 +151,46 @@ void raw_free(silh_ctx* c, void* p) {
   }
 }
 
-template <class T>
-silh_status dalloc(silh_ctx* c, std::vector<void*>& list, T** out, size_t count) {
-  void* p = raw_alloc(c, count * sizeof(T));
-  if (!p) return fail(SILH_E_NOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
-  list.push_back(p);
-  *out = (T*)p;
-  return SILH_OK;
-}
+// Buffers of one stage are carved out of a single allocation (one allocator
+// call per stage instead of one per buffer), each at a 256-byte boundary.
+struct Carve {
+  struct Req {
+    void** out;
+    size_t bytes;
+  };
+  std::vector<Req> reqs;
+  template <class T>
+  Carve& add(T** out, size_t count) {
+    reqs.push_back({(void**)out, count * sizeof(T)});
+    return *this;
+  }
+  // every request gets an address of its own, also an empty one
+  static size_t span(size_t b) { return b == 0 ? 256 : (b + 255) / 256 * 256; }
+  silh_status commit(silh_ctx* c, std::vector<void*>& list) {
+    size_t tot = 0;
+    for (const Req& r : reqs) tot += span(r.bytes);
+    void* base = raw_alloc(c, tot);
+    if (!base) return fail(SILH_E_NOMEM, "device allocation of %zu bytes failed", tot);
+    list.push_back(base);
+    size_t off = 0;
+    for (const Req& r : reqs) {
+      *r.out = (void*)((char*)base + off);
+      off += span(r.bytes);
+    }
+    return SILH_OK;
+  }
+};
 
 void free_list(silh_ctx* c, std::vector<void*>& list) {
   for (void* p : list) raw_free(c, p);
   list.clear();
 }
+
+// Timing events outlive the contexts that used them: a per-device pool
+// shared by every context of the process (creating events per request costs
+// more than the short kernels they time).
+std::mutex g_event_mu;
+std::map<int, std::vector<hipEvent_t>> g_event_pool;
 
 hipEvent_t get_event(silh_ctx* c) {
   if (!c->pool.empty()) {
@@ -169,9 +198,32 @@ hipEvent_t get_event(silh_ctx* c) {
     c->pool.pop_back();
     return e;
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    auto& v = g_event_pool[dev];
+    if (!v.empty()) {
+      hipEvent_t e = v.back();
+      v.pop_back();
+      return e;
+    }
+  }
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
+}
+
+void return_events(std::vector<hipEvent_t>& evs) {
+  int dev = 0;
+  if (evs.empty()) return;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  } else {
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    auto& v = g_event_pool[dev];
+    v.insert(v.end(), evs.begin(), evs.end());
+  }
+  evs.clear();
 }
 
 // Brackets a kernel launch with events when profiling is on, and checks the
@@ -266,8 +318,13 @@ silh_status check_params(const silh_params* prm, const float* X, const int32_t* 
 // Cluster sizes, offsets and the stable sort by label.
 silh_status build_index(silh_ctx* c) {
   const int n = c->n, k = c->k;
-  CHK(dalloc(c, c->alloc_init, &c->csize, (size_t)k));
-  CHK(dalloc(c, c->alloc_init, &c->bad, 1));
+  const int units = (int)ceil_div(n, kSortSeg);
+  {
+    Carve cv;
+    cv.add(&c->csize, (size_t)k).add(&c->bad, 1).add(&c->off, (size_t)k + 1).add(&c->q, (size_t)k);
+    cv.add(&c->uh, (size_t)units * k).add(&c->perm, (size_t)n).add(&c->slab, (size_t)n);
+    CHK(cv.commit(c, c->alloc_init));
+  }
   HIPCHK(hipMemsetAsync(c->csize, 0, (size_t)k * sizeof(int32_t), c->st));
   HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
   {
@@ -299,14 +356,8 @@ silh_status build_index(silh_ctx* c) {
       c->q_h[j] = qj < 1.0 ? qj : 1.0;
     }
   }
-  CHK(dalloc(c, c->alloc_init, &c->off, (size_t)k + 1));
-  CHK(dalloc(c, c->alloc_init, &c->q, (size_t)k));
   CHK(h2d(c, c->off, c->off_h));
   CHK(h2d(c, c->q, c->q_h));
-  const int units = (int)ceil_div(n, kSortSeg);
-  CHK(dalloc(c, c->alloc_init, &c->uh, (size_t)units * k));
-  CHK(dalloc(c, c->alloc_init, &c->perm, (size_t)n));
-  CHK(dalloc(c, c->alloc_init, &c->slab, (size_t)n));
   {
     Launch L(c, K_SORT_HIST);
     launch_unit_hist(c->st, c->labels, n, k, c->uh);
@@ -364,7 +415,6 @@ silh_status compact_and_pack(silh_ctx* c) {
     launch_scan(c->st, c->flag, n, c->pos, c->scan_tmp);
     CHK(L.done());
   }
-  CHK(dalloc(c, c->alloc_sample, &c->s_off, (size_t)k + 1));
   launch_gather_at(c->st, c->pos, c->off, k, c->s_off);
   HIPCHK(hipGetLastError());
   c->s_off32_h.assign(k + 1, 0);
@@ -380,19 +430,26 @@ silh_status compact_and_pack(silh_ctx* c) {
   }
   c->S = c->s_off_h[k];
   c->S_pad = c->sp_off_h[k];
-  CHK(dalloc(c, c->alloc_sample, &c->sp_off, (size_t)k + 1));
-  CHK(dalloc(c, c->alloc_sample, &c->cnt, (size_t)k));
+  const int prec = c->mprec;
+  const int KP = c->mfma ? mfma_kp(prec, c->DM) : 0;
+  const bool mfma_pack = c->mfma && c->S_pad > 0;
+  {
+    Carve cv;
+    cv.add(&c->gid_view, (size_t)c->S).add(&c->gid_pk, (size_t)c->S_pad).add(&c->w32, (size_t)c->S_pad);
+    cv.add(&c->aux32, (size_t)c->S_pad).add(&c->Y32, (size_t)c->S_pad * c->DM);
+    unsigned char* ym = nullptr;
+    if (mfma_pack) {
+      cv.add(&c->mu, (size_t)k * KP).add(&c->bnorm, (size_t)c->S_pad);
+      cv.add(&ym, (size_t)c->S_pad * KP * (prec == 0 ? 4 : (prec == 1 ? 2 : 1)));
+    }
+    CHK(cv.commit(c, c->alloc_sample));
+    c->Ym = ym;
+  }
   CHK(h2d(c, c->sp_off, c->sp_off_h));
   CHK(h2d(c, c->cnt, c->cnt_h));
-  CHK(dalloc(c, c->alloc_sample, &c->gid_view, (size_t)c->S));
-  CHK(dalloc(c, c->alloc_sample, &c->gid_pk, (size_t)c->S_pad));
-  CHK(dalloc(c, c->alloc_sample, &c->w32, (size_t)c->S_pad));
-  CHK(dalloc(c, c->alloc_sample, &c->aux32, (size_t)c->S_pad));
-  CHK(dalloc(c, c->alloc_sample, &c->Y32, (size_t)c->S_pad * c->DM));
   HIPCHK(hipMemsetAsync(c->gid_pk, 0xFF, (size_t)c->S_pad * sizeof(int32_t), c->st));
-  HIPCHK(hipMemsetAsync(c->w32, 0, (size_t)c->S_pad * sizeof(float), c->st));
-  HIPCHK(hipMemsetAsync(c->aux32, 0, (size_t)c->S_pad * sizeof(float), c->st));
-  HIPCHK(hipMemsetAsync(c->Y32, 0, (size_t)c->S_pad * c->DM * sizeof(float), c->st));
+  // w32, aux32 and Y32 are consecutive in the stage's allocation: one clear
+  HIPCHK(hipMemsetAsync(c->w32, 0, (size_t)((char*)(c->Y32 + (size_t)c->S_pad * c->DM) - (char*)c->w32), c->st));
   {
     Launch L(c, K_PACK);
     launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, c->d, c->DM, c->p_gid, c->s_off,
@@ -400,15 +457,7 @@ silh_status compact_and_pack(silh_ctx* c) {
                 c->Y32);
     CHK(L.done());
   }
-  if (c->mfma && c->S_pad > 0) {
-    const int prec = c->mprec;
-    const int KP = mfma_kp(prec, c->DM);
-    CHK(dalloc(c, c->alloc_sample, &c->mu, (size_t)k * KP));
-    CHK(dalloc(c, c->alloc_sample, &c->bnorm, (size_t)c->S_pad));
-    void* ym = raw_alloc(c, (size_t)c->S_pad * KP * (prec == 0 ? 4 : (prec == 1 ? 2 : 1)));
-    if (!ym) return fail(SILH_E_NOMEM, "device allocation of the packed sample failed");
-    c->alloc_sample.push_back(ym);
-    c->Ym = ym;
+  if (mfma_pack) {
     {
       Launch L(c, K_CENTER);
       launch_center(c->st, c->Y32, c->DM, KP, c->sp_off, c->cnt, k, c->mu);
@@ -422,9 +471,6 @@ silh_status compact_and_pack(silh_ctx* c) {
       CHK(L.done());
     }
   }
-  const int nb = (int)ceil_div(n, c->p2_rows);
-  CHK(dalloc(c, c->alloc_sample, &c->bpart, (size_t)nb));
-  CHK(dalloc(c, c->alloc_sample, &c->mean_d, 1));
   c->state = 1;
   return SILH_OK;
 }
@@ -432,18 +478,23 @@ silh_status compact_and_pack(silh_ctx* c) {
 silh_status sample_stage_buffers(silh_ctx* c) {
   free_list(c, c->alloc_sample);
   c->state = 0;
-  const int n = c->n;
-  CHK(dalloc(c, c->alloc_sample, &c->flag, (size_t)n));
-  CHK(dalloc(c, c->alloc_sample, &c->pos, (size_t)n + 1));
-  CHK(dalloc(c, c->alloc_sample, &c->scan_tmp, (size_t)ceil_div(n, kScanTile) + 1));
-  CHK(dalloc(c, c->alloc_sample, &c->p_gid, (size_t)n));
-  return SILH_OK;
+  c->f0_gid = c->gid_view = nullptr;
+  c->f0_cl = c->items = c->citem_first = c->citem_count = c->gid_pk = nullptr;
+  c->f0X = c->W0 = c->partial = nullptr;
+  c->w32 = c->aux32 = c->Y32 = c->mu = c->bnorm = nullptr;
+  c->Ym = nullptr;
+  const int n = c->n, k = c->k;
+  const int nb = (int)ceil_div(n, c->p2_rows);
+  Carve cv;
+  cv.add(&c->flag, (size_t)n).add(&c->pos, (size_t)n + 1).add(&c->scan_tmp, (size_t)ceil_div(n, kScanTile) + 1);
+  cv.add(&c->p_gid, (size_t)n).add(&c->f0_off, (size_t)k + 1).add(&c->s_off, (size_t)k + 1);
+  cv.add(&c->sp_off, (size_t)k + 1).add(&c->cnt, (size_t)k).add(&c->bpart, (size_t)nb).add(&c->mean_d, 1);
+  return cv.commit(c, c->alloc_sample);
 }
 
 silh_status phase1(silh_ctx* c) {
   const int n = c->n, k = c->k, d = c->d;
   CHK(sample_stage_buffers(c));
-  CHK(dalloc(c, c->alloc_sample, &c->f0_off, (size_t)k + 1));
   c->F0 = 0;
   c->f0_off_h.assign(k + 1, 0);
   c->f0_off32_h.assign(k + 1, 0);
@@ -469,22 +520,12 @@ silh_status phase1(silh_ctx* c) {
   } else {
     HIPCHK(hipMemsetAsync(c->f0_off, 0, (size_t)(k + 1) * sizeof(int32_t), c->st));
   }
-  CHK(dalloc(c, c->alloc_sample, &c->f0_gid, (size_t)c->F0));
-  CHK(dalloc(c, c->alloc_sample, &c->f0_cl, (size_t)c->F0));
-  CHK(dalloc(c, c->alloc_sample, &c->f0X, (size_t)c->F0 * c->DM));
-  CHK(dalloc(c, c->alloc_sample, &c->W0, (size_t)c->F0));
+  // work items for W(e_bar)
+  c->items_h.clear();
+  c->citem_first_h.assign(k, 0);
+  c->citem_count_h.assign(k, 0);
+  int64_t pbase = 0;
   if (pps && c->F0 > 0) {
-    {
-      Launch L(c, K_F0_PACK);
-      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, c->f0_gid, c->f0_cl,
-                     c->f0X);
-      CHK(L.done());
-    }
-    // work items for W(e_bar)
-    c->items_h.clear();
-    c->citem_first_h.assign(k, 0);
-    c->citem_count_h.assign(k, 0);
-    int64_t pbase = 0;
     for (int j = 0; j < k; ++j) {
       const int fj = c->f0_off32_h[j + 1] - c->f0_off32_h[j];
       c->citem_first_h[j] = (int32_t)(c->items_h.size() / 6);
@@ -497,11 +538,22 @@ silh_status phase1(silh_ctx* c) {
       }
       if (pbase > (int64_t)1 << 30) return fail(SILH_E_ARG, "initial sample too large");
     }
-    const int nitems = (int)(c->items_h.size() / 6);
-    CHK(dalloc(c, c->alloc_sample, &c->items, c->items_h.size()));
-    CHK(dalloc(c, c->alloc_sample, &c->citem_first, (size_t)k));
-    CHK(dalloc(c, c->alloc_sample, &c->citem_count, (size_t)k));
-    CHK(dalloc(c, c->alloc_sample, &c->partial, (size_t)pbase));
+  }
+  const int nitems = (int)(c->items_h.size() / 6);
+  {
+    Carve cv;
+    cv.add(&c->f0_gid, (size_t)c->F0).add(&c->f0_cl, (size_t)c->F0).add(&c->f0X, (size_t)c->F0 * c->DM);
+    cv.add(&c->W0, (size_t)c->F0).add(&c->items, c->items_h.size()).add(&c->citem_first, (size_t)k);
+    cv.add(&c->citem_count, (size_t)k).add(&c->partial, (size_t)pbase);
+    CHK(cv.commit(c, c->alloc_sample));
+  }
+  if (pps && c->F0 > 0) {
+    {
+      Launch L(c, K_F0_PACK);
+      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, c->f0_gid, c->f0_cl,
+                     c->f0X);
+      CHK(L.done());
+    }
     CHK(h2d(c, c->items, c->items_h));
     CHK(h2d(c, c->citem_first, c->citem_first_h));
     CHK(h2d(c, c->citem_count, c->citem_count_h));
@@ -682,7 +734,7 @@ void silh_destroy(silh_ctx* c) {
     c->pool.push_back(p.b);
   }
   c->pending.clear();
-  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  return_events(c->pool);
   free_list(c, c->alloc_sample);
   free_list(c, c->alloc_init);
   delete c;

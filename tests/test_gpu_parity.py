@@ -314,6 +314,49 @@ def test_allocator_failure_reports_nomem():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("fail_at", [1, 2, 3, 4])
+def test_allocator_failure_mid_request(fail_at):
+    """The allocator fails at its fail_at-th call (the index, the per-sampling
+    buffers, the F0 buffers, the sample buffers): the failing call reports
+    SILH_E_NOMEM, every block handed out is freed exactly once."""
+    import ctypes
+    lib = native.load_library()
+    X, L = synth.tiny_case(3000, 5, 4, seed=2)
+    Xd, Ld = dev(X, L)
+    live, calls, freed_twice = {}, [0], []
+
+    def alloc(nbytes, user):
+        calls[0] += 1
+        if calls[0] >= fail_at + 1:
+            return None
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(ptr, user):
+        if ptr not in live:
+            freed_twice.append(ptr)
+        live.pop(ptr, None)
+
+    afn, ffn = native.ALLOC_FN(alloc), native.FREE_FN(free)
+    p = native._params(3000, 5, 4, "eucl", "bf16", "pps", 64, 0.0, 0.01, 0, use_torch_alloc=False)
+    p.alloc, p.free = afn, ffn
+    out = ctypes.c_void_p()
+    st = lib.silh_sample_init(ctypes.byref(p), ctypes.c_void_p(Xd.data_ptr()),
+                              ctypes.c_void_p(Ld.data_ptr()), None, ctypes.byref(out))
+    assert native.STATUS[st] == "SILH_OK"   # the index is the first call
+    S = ctypes.c_int64()
+    st = lib.silh_pps_sample(out, ctypes.byref(S), None)
+    if fail_at <= 3:
+        assert native.STATUS[st] == "SILH_E_NOMEM"
+    else:
+        assert native.STATUS[st] == "SILH_OK"
+    lib.silh_destroy(out)
+    torch.cuda.synchronize()
+    assert not freed_twice
+    assert not live
+
+
 # ---------------------------------------------------------------------------
 # full size: n=1e6, d=32, k=16 Zipf Gaussian blobs, t=256 (the benchmark workload)
 # ---------------------------------------------------------------------------
