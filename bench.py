@@ -150,6 +150,27 @@ def run_steps(native, Xd, Ld, k, metric, prec, t, seed, steps, warmup, out_a, ou
     return {"S": S, "mean": mean, "t_all": t_all, "times": times, "stats": stats, "info": info}
 
 
+def run_rows(native, torch, Xd, Ld, k, metric, prec, t, seed, steps, full_mean, eps=0.01, delta=0.01):
+    """gl-pps-s (Eq. 10): Phase 1 as in a full request, then Phase 2 only for
+    m = ceil((2/eps^2) ln(2/delta)) uniform row draws."""
+    n = Xd.shape[0]
+    m = native.silh_rows_for(eps, delta)
+    times, mean, S = [], None, 0
+    for i in range(steps + 1):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, "pps", t=t, delta=0.01, seed=seed)
+        S, _ = native.silh_pps_sample(ctx)
+        rows = native.silh_draw_rows(seed + 1000, n, m)
+        mean = native.silh_scores_rows(ctx, rows, a=False, b=False, s=False, mean=True)["mean"]
+        native.silh_destroy(ctx)
+        if i > 0:   # the first request is a warm-up
+            times.append(time.perf_counter() - ts)
+    t_req = sum(times) / len(times)
+    return {"m": m, "eps2": eps, "delta2": delta, "ms_per_request": t_req * 1e3,
+            "phase2_pairs": m * S, "s_bar": mean, "abs_delta_vs_s_hat_2": abs(mean - full_mean)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +243,10 @@ def main():
             "value": w2 / (r["t_all"] / args.compare_steps), "ms_per_step": r["t_all"] / args.compare_steps * 1e3,
             "phase2_ms": m2 / max(c2, 1),
             "phase2_roofline": phase2_roofline("manh", "fp32", d, n, r["S"], m2 / max(c2, 1) / 1e3)}
+
+    if args.compare_steps > 0:
+        compare["gl_pps_s"] = run_rows(native, torch, Xd, Ld, k, args.metric, args.prec, t, seed,
+                                       args.compare_steps, main_run["mean"])
 
     times_ms = np.array(main_run["times"]) * 1e3
     out = {

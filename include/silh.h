@@ -176,6 +176,52 @@ silh_status silh_scores(silh_ctx* ctx, float* a, float* b, float* s, double* s_m
 silh_status silh_exact(const silh_params* prm, const float* X, const int32_t* labels,
                        silh_stream stream, float* a, float* b, float* s, double* s_mean_host);
 
+/*
+ * Subsampled estimates of s(C) (Section 4.2).  The m rows are drawn
+ * independently and uniformly from {0..n-1}, with replacement (Eqs. 8 and 10;
+ * the Hoeffding bounds after them need independent draws).
+ *
+ * silh_rows_for - the sample size of those bounds, m = ceil((2/eps^2)
+ * ln(2/delta)), into *m.  SILH_E_ARG unless eps, delta lie in (0, 1) and m
+ * fits 2^30.
+ */
+silh_status silh_rows_for(double eps, double delta, int64_t* m);
+
+/*
+ * silh_draw_rows - rows[i] = floor(B_i * n / 2^53) for i in [0, m), B_i the
+ * 53 bits of the Philox4x32-10 draw of counter i in draw stream 3 (the same
+ * generator and bit layout as the Poisson draws), computed in integers.
+ *  rows   [m] int32, device, caller-owned.  Enqueued on stream; no sync.
+ * SILH_E_ARG for n outside [1, 2^30], m outside [0, 2^30], NULL rows (m > 0).
+ */
+silh_status silh_draw_rows(uint64_t seed, int64_t n, int64_t m, int32_t* rows, silh_stream stream);
+
+/*
+ * silh_scores_rows - gl-pps-s (PPS context) or gl-uni-s (uniform context),
+ * Eq. 10: a_hat, b_hat, s_hat of Algorithm 1, Phase 2, for the m entries of
+ * rows (duplicates allowed; entry i gets the values of element rows[i]) and
+ * their mean (1/m) sum_i s_hat(rows[i]).  Only the distinct rows are
+ * evaluated.
+ *  rows          [m] int32, device, each in [0, n); unchanged.
+ *  a, b, s       [m] float32, device, each nullable.
+ *  s_mean_host   the mean (float64 with compensation), nullable.
+ * Synchronises the stream (the number of distinct rows is read back).
+ * SILH_E_STATE before a successful silh_pps_sample; SILH_E_ARG for NULL rows,
+ * m outside [1, 2^30] or an entry outside [0, n) (then nothing is written).
+ */
+silh_status silh_scores_rows(silh_ctx* ctx, const int32_t* rows, int64_t m, float* a, float* b,
+                             float* s, double* s_mean_host);
+
+/*
+ * silh_exact_rows - gl-s, Eq. 8: the exact a(e), b(e), s(e) (Eqs. 1-2) of
+ * the m entries of rows and their mean.  Arguments as silh_exact and
+ * silh_scores_rows; the cost is m' * n distance evaluations for m' distinct
+ * rows.
+ */
+silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_t* labels,
+                            const int32_t* rows, int64_t m, silh_stream stream, float* a, float* b,
+                            float* s, double* s_mean_host);
+
 /* Read-only view of a context's Phase-1 result (for inspection and tests). */
 typedef struct {
   int64_t S;                  /* sum_j |F_j|                                              */

@@ -9,12 +9,15 @@ Modules:
   distance    the four distances of the experiments, float64.
   silhouette  exact silhouette, Phase 1 / Phase 2 of Algorithm 1, the
               uniform-sampling variant and the global mean (Eq. 9).
+  global_est  the subsampled global estimators gl-s (Eq. 8) and
+              gl-pps-s / gl-uni-s (Eq. 10).
 
 Parity status: every function here is pinned by tests in tests/test_oracle_*.py
 against values the paper prints, closed forms, brute force or invariants; none
 is "parity unpinned".
 """
 from .distance import CANB, COS, EUCL, MANH, dist_matrix, dist_to_point, metric_id  # noqa: F401
-from .philox import STREAM_F0, STREAM_PPS, STREAM_UNI, philox4x32_10, uniform53  # noqa: F401
+from .philox import STREAM_F0, STREAM_PPS, STREAM_ROWS, STREAM_UNI, bits53, philox4x32_10, uniform53  # noqa: F401
 from .silhouette import (cluster_members, default_t, estimate, exact, global_mean,  # noqa: F401
                          pps_silhouette, sample, scores_from_weights)
+from .global_est import draw_rows, gl_pps_s, gl_s, m_for, subset_mean  # noqa: F401

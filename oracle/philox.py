@@ -27,6 +27,7 @@ W1 = np.uint64(0xBB67AE85)
 STREAM_F0 = 0   # initial sample F^0 (Algorithm 1, Phase 1, Poisson draw with fixed rate)
 STREAM_PPS = 1  # final PPS sample F (Algorithm 1, Poisson draw with rates p_e)
 STREAM_UNI = 2  # uniform Poisson sample (Section 4.1.3)
+STREAM_ROWS = 3  # the m row indices of the subsampled global estimators (Section 4.2)
 
 
 def philox4x32_10(ctr, key):
@@ -46,13 +47,18 @@ def philox4x32_10(ctr, key):
     return c0, c1, c2, c3
 
 
-def uniform53(seed: int, gid, stream: int) -> np.ndarray:
-    """U(seed, gid, stream) in [0, 1) as float64, vectorised over gid."""
+def bits53(seed: int, gid, stream: int) -> np.ndarray:
+    """The 53-bit integer w0 * 2^21 + floor(w1 / 2^11) behind U(seed, gid,
+    stream), as uint64, vectorised over gid."""
     gid = np.asarray(gid, dtype=np.uint64)
     seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     key = (np.uint64(seed & 0xFFFFFFFF), np.uint64(seed >> 32))
     ctr = (gid & MASK32, gid >> np.uint64(32), np.full(gid.shape, stream, dtype=np.uint64),
            np.zeros(gid.shape, dtype=np.uint64))
     w0, w1, _, _ = philox4x32_10(ctr, key)
-    mant = (w0 << np.uint64(21)) | (w1 >> np.uint64(11))   # 53-bit integer
-    return mant.astype(np.float64) * (2.0 ** -53)
+    return (w0 << np.uint64(21)) | (w1 >> np.uint64(11))
+
+
+def uniform53(seed: int, gid, stream: int) -> np.ndarray:
+    """U(seed, gid, stream) in [0, 1) as float64, vectorised over gid."""
+    return bits53(seed, gid, stream).astype(np.float64) * (2.0 ** -53)

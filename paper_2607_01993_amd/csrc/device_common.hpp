@@ -31,19 +31,25 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
   }
 }
 
-// 53-bit uniform in [0,1) for element `gid` in draw `stream`: counter
-// (gid_lo, gid_hi, stream, 0), key (seed_lo, seed_hi), first two words.
-__device__ __forceinline__ double uniform53(uint64_t seed, uint64_t gid, uint32_t stream) {
+// 53 random bits for element `gid` in draw `stream`: counter
+// (gid_lo, gid_hi, stream, 0), key (seed_lo, seed_hi), first two words as
+// w0 * 2^21 + floor(w1 / 2^11).
+__device__ __forceinline__ uint64_t bits53(uint64_t seed, uint64_t gid, uint32_t stream) {
   uint32_t c0 = (uint32_t)gid, c1 = (uint32_t)(gid >> 32), c2 = stream, c3 = 0u;
   philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
-  const uint64_t mant = ((uint64_t)c0 << 21) | (uint64_t)(c1 >> 11);
-  return (double)mant * 0x1.0p-53;
+  return ((uint64_t)c0 << 21) | (uint64_t)(c1 >> 11);
+}
+
+// the uniform in [0,1) built from those bits
+__device__ __forceinline__ double uniform53(uint64_t seed, uint64_t gid, uint32_t stream) {
+  return (double)bits53(seed, gid, stream) * 0x1.0p-53;
 }
 
 // Draw ids.
 constexpr uint32_t kStreamF0 = 0;
 constexpr uint32_t kStreamPPS = 1;
 constexpr uint32_t kStreamUNI = 2;
+constexpr uint32_t kStreamRows = 3;  // row draws of the subsampled global estimators
 
 // Metric ids (same numbering as the C ABI).
 constexpr int kEucl = 0, kCos = 1, kManh = 2, kCanb = 3;

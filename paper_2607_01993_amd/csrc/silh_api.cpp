@@ -85,7 +85,7 @@ struct silh_ctx {
   int p2_rows = kP2Rows;
   int state = 0;  // 0 = indexed, 1 = sampled
 
-  std::vector<void*> alloc_init, alloc_sample;
+  std::vector<void*> alloc_init, alloc_sample, alloc_rows;
 
   // host copies
   std::vector<uint32_t> counts_h;
@@ -619,6 +619,85 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
   return SILH_OK;
 }
 
+// Phase 2 for the entries of rows[0..m) (duplicates allowed): the distinct
+// rows are gathered into a contiguous block and run through the same Phase-2
+// kernels, with the sample's ids renumbered into that block so that the
+// self-pair test still finds each element's own column.
+silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, float* b, float* s,
+                        double* mean_host) {
+  if (!rows) return fail(SILH_E_ARG, "rows is NULL");
+  if (m < 1 || m > kMaxN) return fail(SILH_E_ARG, "m=%lld outside [1, 2^30]", (long long)m);
+  free_list(c, c->alloc_rows);
+  const int n = c->n, d = c->d;
+  const int64_t cap = m < n ? m : n;  // distinct rows
+  int32_t *mark = nullptr, *pos = nullptr, *tmp = nullptr, *urows = nullptr, *ls = nullptr, *gsub = nullptr;
+  int* bad = nullptr;
+  float *Xs = nullptr, *au = nullptr, *bu = nullptr, *su = nullptr;
+  double *bpu = nullptr, *bpm = nullptr, *mean_d = nullptr;
+  const int64_t nbm = ceil_div(m, kRowsBlock);
+  {
+    Carve cv;
+    cv.add(&mark, (size_t)n).add(&pos, (size_t)n + 1).add(&tmp, (size_t)ceil_div(n, kScanTile) + 1);
+    cv.add(&urows, (size_t)cap).add(&bad, 1).add(&Xs, (size_t)cap * d).add(&ls, (size_t)cap);
+    cv.add(&gsub, (size_t)c->S_pad).add(&au, (size_t)cap).add(&bu, (size_t)cap).add(&su, (size_t)cap);
+    cv.add(&bpu, (size_t)ceil_div(cap, c->p2_rows)).add(&bpm, (size_t)nbm).add(&mean_d, 1);
+    CHK(cv.commit(c, c->alloc_rows));
+  }
+  HIPCHK(hipMemsetAsync(mark, 0, (size_t)n * sizeof(int32_t), c->st));
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), c->st));
+  launch_rows_mark(c->st, rows, m, n, mark, bad);
+  HIPCHK(hipGetLastError());
+  launch_scan(c->st, mark, n, pos, tmp);
+  HIPCHK(hipGetLastError());
+  int32_t mu_h = 0;
+  int bad_h = 0;
+  HIPCHK(hipMemcpyAsync(&mu_h, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (bad_h) return fail(SILH_E_ARG, "a row index lies outside [0, %d)", n);
+  const int mu = mu_h;
+  launch_rows_compact(c->st, mark, pos, n, urows);
+  launch_rows_gather(c->st, c->X, c->labels, d, urows, mu, Xs, ls);
+  launch_rows_remap(c->st, c->gid_pk, c->S_pad, urows, mu, gsub);
+  HIPCHK(hipGetLastError());
+  P2Args A;
+  A.X = Xs;
+  A.n = mu;
+  A.d = d;
+  A.labels = ls;
+  A.Y = c->Y32;
+  A.w = c->w32;
+  A.aux = c->aux32;
+  A.gid_pk = gsub;
+  A.sp_off = c->sp_off;
+  A.cnt = c->cnt;
+  A.csize = c->csize;
+  A.k = c->k;
+  A.a = au;
+  A.b = bu;
+  A.s = su;
+  A.What = nullptr;
+  A.bpart = bpu;
+  {
+    Launch L(c, K_PHASE2);
+    const bool ok = c->mfma ? launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym,
+                                                 c->bnorm)
+                            : launch_phase2_valu(c->st, c->prm.metric, c->DM, A);
+    if (!ok) return fail(SILH_E_UNSUPPORTED, "no Phase-2 kernel for metric %d, d=%d", c->prm.metric, c->d);
+    CHK(L.done());
+  }
+  launch_rows_expand(c->st, rows, m, urows, mu, au, bu, su, a, b, s, bpm);
+  HIPCHK(hipGetLastError());
+  if (mean_host) {
+    launch_mean(c->st, bpm, (int)nbm, m, mean_d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&c->mean_h, mean_d, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    *mean_host = c->mean_h;
+  }
+  return SILH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -668,6 +747,51 @@ silh_status silh_exact(const silh_params* prm, const float* X, const int32_t* la
   }
   if (st == SILH_OK) st = compact_and_pack(c);
   if (st == SILH_OK) st = run_phase2(c, a, b, s, nullptr, s_mean_host);
+  std::string msg = g_err;
+  silh_destroy(c);
+  g_err = msg;
+  return st;
+}
+
+silh_status silh_rows_for(double eps, double delta, int64_t* m) {
+  if (!m) return fail(SILH_E_ARG, "m is NULL");
+  if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0))
+    return fail(SILH_E_ARG, "eps and delta must lie in (0, 1)");
+  const double v = std::ceil((2.0 / (eps * eps)) * std::log(2.0 / delta));
+  if (!(v <= (double)kMaxN)) return fail(SILH_E_ARG, "m=%g exceeds 2^30", v);
+  *m = (int64_t)v;
+  return SILH_OK;
+}
+
+silh_status silh_draw_rows(uint64_t seed, int64_t n, int64_t m, int32_t* rows, silh_stream stream) {
+  if (n < 1 || n > kMaxN) return fail(SILH_E_ARG, "n=%lld outside [1, 2^30]", (long long)n);
+  if (m < 0 || m > kMaxN) return fail(SILH_E_ARG, "m=%lld outside [0, 2^30]", (long long)m);
+  if (m > 0 && !rows) return fail(SILH_E_ARG, "rows is NULL");
+  launch_rows_draw((hipStream_t)stream, seed, n, m, rows);
+  HIPCHK(hipGetLastError());
+  return SILH_OK;
+}
+
+silh_status silh_scores_rows(silh_ctx* c, const int32_t* rows, int64_t m, float* a, float* b, float* s,
+                             double* s_mean_host) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  if (c->state != 1) return fail(SILH_E_STATE, "silh_scores_rows before a successful silh_pps_sample");
+  return rows_phase2(c, rows, m, a, b, s, s_mean_host);
+}
+
+silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_t* labels,
+                            const int32_t* rows, int64_t m, silh_stream stream, float* a, float* b,
+                            float* s, double* s_mean_host) {
+  silh_ctx* c = nullptr;
+  CHK(create(prm, X, labels, stream, true, &c));
+  silh_status st = sample_stage_buffers(c);
+  if (st == SILH_OK) {
+    Launch L(c, K_DRAW);
+    launch_fill_all(c->st, c->perm, c->n, c->p_gid, c->flag);
+    st = L.done();
+  }
+  if (st == SILH_OK) st = compact_and_pack(c);
+  if (st == SILH_OK) st = rows_phase2(c, rows, m, a, b, s, s_mean_host);
   std::string msg = g_err;
   silh_destroy(c);
   g_err = msg;
@@ -735,6 +859,7 @@ void silh_destroy(silh_ctx* c) {
   }
   c->pending.clear();
   return_events(c->pool);
+  free_list(c, c->alloc_rows);
   free_list(c, c->alloc_sample);
   free_list(c, c->alloc_init);
   delete c;

@@ -97,6 +97,27 @@ bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Ar
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
 
+// ---- subsampled global estimators (row subsets) ------------------------------
+// rows[i] = floor(B_i * n / 2^53), B_i the 53 Philox bits of counter i in the
+// row stream
+void launch_rows_draw(hipStream_t st, uint64_t seed, int64_t n, int64_t m, int32_t* rows);
+// mark[rows[i]] = 1 for every valid entry; *bad = 1 if any entry lies outside [0, n)
+void launch_rows_mark(hipStream_t st, const int32_t* rows, int64_t m, int n, int32_t* mark, int* bad);
+// urows[pos[i]] = i for every marked i (ascending, distinct)
+void launch_rows_compact(hipStream_t st, const int32_t* mark, const int32_t* pos, int n, int32_t* urows);
+// Xs[i] = X[urows[i]], ls[i] = labels[urows[i]]
+void launch_rows_gather(hipStream_t st, const float* X, const int32_t* labels, int d,
+                        const int32_t* urows, int mu, float* Xs, int32_t* ls);
+// gid_sub[s] = index of gid_pk[s] in urows, or -1 when it is not there
+void launch_rows_remap(hipStream_t st, const int32_t* gid_pk, int64_t S_pad, const int32_t* urows,
+                       int mu, int32_t* gid_sub);
+// a/b/s[i] = a/b/s_u[index of rows[i] in urows]; bpart[block] = float64 sum
+// of the block's s (blocks of kRowsBlock entries)
+constexpr int kRowsBlock = 256;
+void launch_rows_expand(hipStream_t st, const int32_t* rows, int64_t m, const int32_t* urows, int mu,
+                        const float* au, const float* bu, const float* su, float* a, float* b, float* s,
+                        double* bpart);
+
 // ---- diagnostics -------------------------------------------------------------
 void launch_uniform(hipStream_t st, uint64_t seed, int64_t gid0, int64_t count, uint32_t stream_id,
                     double* out);

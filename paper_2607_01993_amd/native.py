@@ -51,6 +51,14 @@ SIGNATURES = {
     "silh_exact": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_double)]),
+    "silh_rows_for": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]),
+    "silh_draw_rows": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "silh_scores_rows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "silh_exact_rows": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "silh_sample_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SilhSampleInfo)]),
     "silh_philox_uniform": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -281,6 +289,90 @@ def silh_exact(X, labels, k, metric="eucl", prec="fp32", stream=None, a=True, b=
     res = {x: v for x, v in outs.items() if v is not None}
     if mean:
         res["mean"] = m.value
+    return res
+
+
+def silh_rows_for(eps, delta) -> int:
+    """m = ceil((2/eps^2) ln(2/delta)) of the subsampled estimators."""
+    lib = load_library()
+    m = ctypes.c_int64()
+    _check(lib.silh_rows_for(float(eps), float(delta), ctypes.byref(m)), "silh_rows_for")
+    return int(m.value)
+
+
+def silh_draw_rows(seed, n, m, stream=None):
+    """m independent uniform row indices in [0, n) (device int32)."""
+    torch = _torch()
+    lib = load_library()
+    st, sh = _stream_handle(stream)
+    rows = torch.empty(max(int(m), 1), dtype=torch.int32, device="cuda")[:int(m)]
+    _check(lib.silh_draw_rows(int(seed) & 0xFFFFFFFFFFFFFFFF, int(n), int(m),
+                              ctypes.c_void_p(rows.data_ptr()), sh), "silh_draw_rows")
+    return rows
+
+
+def _rows_outputs(rows, a, b, s):
+    torch = _torch()
+    if rows.dtype != torch.int32 or rows.dim() != 1 or not rows.is_cuda or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous int32 device vector")
+    m = rows.shape[0]
+    outs = {name: torch.empty(m, dtype=torch.float32, device=rows.device) if want else None
+            for name, want in (("a", a), ("b", b), ("s", s))}
+    ptr = [ctypes.c_void_p(outs[x].data_ptr()) if outs[x] is not None else ctypes.c_void_p()
+           for x in ("a", "b", "s")]
+    return m, outs, ptr
+
+
+def silh_scores_rows(ctx: Context, rows, a=True, b=True, s=True, mean=True):
+    """gl-pps-s / gl-uni-s (Eq. 10): Phase-2 scores of the entries of rows."""
+    lib = load_library()
+    m, outs, ptr = _rows_outputs(rows, a, b, s)
+    mv = ctypes.c_double()
+    with ctx.target():
+        _check(lib.silh_scores_rows(ctx.ptr, ctypes.c_void_p(rows.data_ptr()), m, *ptr,
+                                    ctypes.byref(mv) if mean else None), "silh_scores_rows")
+    res = {x: v for x, v in outs.items() if v is not None}
+    if mean:
+        res["mean"] = mv.value
+    return res
+
+
+def silh_exact_rows(X, labels, k, rows, metric="eucl", prec="fp32", stream=None, a=True, b=True, s=True,
+                    mean=True, use_torch_alloc=True):
+    """gl-s (Eq. 8): exact scores of the entries of rows."""
+    lib = load_library()
+    _check_inputs(X, labels)
+    st, sh = _stream_handle(stream)
+    p = _params(X.shape[0], X.shape[1], k, metric, prec, "pps", 1, 0.0, 0.5, 0, use_torch_alloc)
+    m, outs, ptr = _rows_outputs(rows, a, b, s)
+    mv = ctypes.c_double()
+    with _Target(X.device.index, st):
+        _check(lib.silh_exact_rows(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()),
+                                   ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(rows.data_ptr()), m,
+                                   sh, *ptr, ctypes.byref(mv) if mean else None), "silh_exact_rows")
+    res = {x: v for x, v in outs.items() if v is not None}
+    if mean:
+        res["mean"] = mv.value
+    return res
+
+
+def gl_s(X, labels, k, m, seed, metric="eucl", prec="fp32"):
+    """Eq. 8: mean of the exact silhouette over m uniform draws of rows."""
+    rows = silh_draw_rows(seed, X.shape[0], m)
+    res = silh_exact_rows(X, labels, k, rows, metric, prec)
+    res["rows"] = rows
+    return res
+
+
+def gl_pps_s(X, labels, k, m, t, seed, rows_seed, metric="eucl", prec="fp32", sampler="pps", delta=0.01):
+    """Eq. 10 (gl-pps-s; gl-uni-s with sampler="uni"): Phase 1, then the
+    Phase-2 scores of m uniform draws of rows and their mean."""
+    ctx = silh_sample_init(X, labels, k, metric, prec, sampler, t=t, delta=delta, seed=seed)
+    silh_pps_sample(ctx)
+    rows = silh_draw_rows(rows_seed, X.shape[0], m)
+    res = silh_scores_rows(ctx, rows)
+    res["rows"] = rows
+    silh_destroy(ctx)
     return res
 
 

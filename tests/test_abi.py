@@ -85,3 +85,35 @@ def test_null_arguments():
     assert lib.silh_exact(ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8), None,
                           None, None, None, None) == 1
     lib.silh_destroy(None)   # no-op
+
+
+def test_rows_for_matches_the_hoeffding_size():
+    """silh_rows_for is host arithmetic: compare it with the oracle's m and with
+    the tail bound 2 exp(-m eps^2 / 2) <= delta that m is chosen for."""
+    import math
+
+    import oracle
+    lib = native.load_library()
+    for eps, delta in ((0.01, 0.01), (0.05, 0.1), (0.2, 0.5), (0.5, 0.01), (0.003, 0.05)):
+        m = ctypes.c_int64()
+        assert lib.silh_rows_for(eps, delta, ctypes.byref(m)) == 0
+        assert m.value == oracle.m_for(eps, delta)
+        assert 2.0 * math.exp(-m.value * eps * eps / 2.0) <= delta * (1 + 1e-12)
+        assert 2.0 * math.exp(-(m.value - 1) * eps * eps / 2.0) > delta
+    m = ctypes.c_int64()
+    for eps, delta in ((0.0, 0.1), (1.0, 0.1), (0.1, 0.0), (0.1, 1.0), (1e-6, 0.01)):
+        assert lib.silh_rows_for(eps, delta, ctypes.byref(m)) == 1, (eps, delta)
+    assert lib.silh_rows_for(0.1, 0.1, None) == 1
+
+
+def test_rows_calls_reject_bad_arguments():
+    lib = native.load_library()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    assert lib.silh_draw_rows(1, 0, 5, fake, None) == 1          # n < 1
+    assert lib.silh_draw_rows(1, 1 << 31, 5, fake, None) == 1    # n > 2^30
+    assert lib.silh_draw_rows(1, 10, -1, fake, None) == 1        # m < 0
+    assert lib.silh_draw_rows(1, 10, 5, None, None) == 1         # rows NULL
+    assert lib.silh_scores_rows(None, fake, 5, None, None, None, None) == 1
+    p = native._params(10, 4, 3, 0, 0, 0, 1, 0.0, 0.5, 0, use_torch_alloc=False)
+    p.k = 1
+    assert lib.silh_exact_rows(ctypes.byref(p), fake, fake, fake, 5, None, None, None, None, None) == 1

@@ -13,60 +13,10 @@ import torch
 
 import oracle
 from paper_2607_01993_amd import native, synth
+from parity_util import (A_B_RTOL, FP8_S_ATOL, LOWP_MEAN_ATOL, LOWP_S_ATOL, S_ATOL,  # noqa: F401
+                         assert_same_sets, compare_scores, dev, mean_tol)
 
 pytestmark = pytest.mark.gpu
-
-A_B_RTOL = 1e-5
-S_ATOL = 4.0e-5
-# bf16 operands (float32 accumulation): per-element and mean bars
-LOWP_S_ATOL = 1e-2
-LOWP_MEAN_ATOL = 1e-3
-# fp8 (e4m3) operands: the element operand's 3-bit mantissa gives each
-# (element, cluster) pair a fixed error of about 0.3 % in W_hat at d = 128, so
-# the per-element bar is wider (measured max 0.017 at n = 4e6, d = 128); the
-# mean bar is the same as bf16
-FP8_S_ATOL = 4e-2
-
-
-def dev(X, L):
-    return torch.from_numpy(X).cuda(), torch.from_numpy(L).cuda()
-
-
-def assert_same_sets(smp_o, view, X_n, seed, sampler, t):
-    """Sample sets equal cluster by cluster, up to float64 decision ties."""
-    k = len(smp_o["F"])
-    assert view["S"] == sum(f.shape[0] for f in smp_o["F"])
-    stream = oracle.STREAM_PPS if sampler == "pps" else oracle.STREAM_UNI
-    for j in range(k):
-        g = view["gid"][view["offsets"][j]:view["offsets"][j + 1]]
-        o = smp_o["F"][j]
-        if not np.array_equal(g, o):
-            diff = np.setxor1d(g, o)
-            u = oracle.uniform53(seed, diff.astype(np.uint64), stream)
-            margin = np.abs(u - smp_o["p"][diff])
-            assert np.all(margin < 1e-12), (j, diff[:10], margin[:10])
-
-
-def compare_scores(gpu, ref, rows=None, prec="fp32"):
-    a = gpu["a"].cpu().numpy().astype(np.float64)
-    b = gpu["b"].cpu().numpy().astype(np.float64)
-    s = gpu["s"].cpu().numpy().astype(np.float64)
-    if rows is not None:
-        a, b, s = a[rows], b[rows], s[rows]
-    if prec in ("fp32", "fp32_valu"):
-        np.testing.assert_allclose(a, ref["a"], rtol=A_B_RTOL, atol=1e-30)
-        np.testing.assert_allclose(b, ref["b"], rtol=A_B_RTOL, atol=1e-30)
-        assert np.max(np.abs(s - ref["s"])) <= S_ATOL
-    else:
-        bar = FP8_S_ATOL if prec == "fp8" else LOWP_S_ATOL
-        err = np.abs(s - ref["s"])
-        print(f"{prec}: max|ds|={err.max():.3e} mean|ds|={err.mean():.3e}")
-        assert err.max() <= bar, err.max()
-    assert np.all(np.abs(s) <= 1.0)
-
-
-def mean_tol(prec):
-    return S_ATOL if prec in ("fp32", "fp32_valu") else LOWP_MEAN_ATOL
 
 
 # (metric, prec) pairs with a Phase-2 kernel: float32 on the matrix cores for
