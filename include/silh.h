@@ -222,6 +222,22 @@ silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_
                             const int32_t* rows, int64_t m, silh_stream stream, float* a, float* b,
                             float* s, double* s_mean_host);
 
+/*
+ * silh_coh_sep - estimates of the cohesion and separation of the clustering
+ * (Appendix B) with W_hat of Algorithm 1, Phase 2, in place of W:
+ *   Coh = (1/2) sum_j sum_{e in C_j} W_hat_{C_j}(e) / sum_j C(|C_j|, 2),
+ *   Sep = sum_{j1<j2} sum_{e in C_j1} W_hat_{C_j2}(e) / sum_{j1<j2} |C_j1||C_j2|
+ * (the printed |C_{j-1}| in the separation denominator read as |C_j1|).
+ * With t >= max |C_j| every p is 1 and these are the exact measures.
+ *  W_hat      [n][k] float32, device, as written by silh_weighted_sums for
+ *             this context; NULL: the call computes it into context memory.
+ *  coh_host, sep_host   the two values (float64 sums); 0 when a denominator
+ *             is 0.  Synchronises the stream.
+ * SILH_E_STATE before a successful silh_pps_sample; SILH_E_ARG for NULL ctx
+ * or outputs.
+ */
+silh_status silh_coh_sep(silh_ctx* ctx, const float* W_hat, double* coh_host, double* sep_host);
+
 /* Read-only view of a context's Phase-1 result (for inspection and tests). */
 typedef struct {
   int64_t S;                  /* sum_j |F_j|                                              */

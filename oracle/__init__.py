@@ -11,6 +11,7 @@ Modules:
               uniform-sampling variant and the global mean (Eq. 9).
   global_est  the subsampled global estimators gl-s (Eq. 8) and
               gl-pps-s / gl-uni-s (Eq. 10).
+  coh_sep     cohesion and separation from cluster sums (Appendix B).
 
 Parity status: every function here is pinned by tests in tests/test_oracle_*.py
 against values the paper prints, closed forms, brute force or invariants; none
@@ -21,3 +22,4 @@ from .philox import STREAM_F0, STREAM_PPS, STREAM_ROWS, STREAM_UNI, bits53, phil
 from .silhouette import (cluster_members, default_t, estimate, exact, global_mean,  # noqa: F401
                          pps_silhouette, sample, scores_from_weights)
 from .global_est import draw_rows, gl_pps_s, gl_s, m_for, subset_mean  # noqa: F401
+from .coh_sep import coh_sep_from_weights  # noqa: F401

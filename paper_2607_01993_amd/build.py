@@ -26,6 +26,7 @@ SOURCES = {
     "k_phase1.hip": ["-ffp-contract=off"],
     "k_phase2_valu.hip": [],
     "k_rows.hip": [],
+    "k_cohsep.hip": [],
     # MFMA results straight into VGPRs (no accumulator-register copies)
     "k_phase2_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }

@@ -798,6 +798,45 @@ silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_
   return st;
 }
 
+silh_status silh_coh_sep(silh_ctx* c, const float* W_hat, double* coh_host, double* sep_host) {
+  if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  if (!coh_host || !sep_host) return fail(SILH_E_ARG, "coh_host or sep_host is NULL");
+  if (c->state != 1) return fail(SILH_E_STATE, "silh_coh_sep before a successful silh_pps_sample");
+  free_list(c, c->alloc_rows);
+  const int n = c->n, k = c->k;
+  const int nb = coh_sep_blocks(n);
+  float* W = nullptr;
+  double *cpart = nullptr, *spart = nullptr, *sums = nullptr;
+  {
+    Carve cv;
+    if (!W_hat) cv.add(&W, (size_t)n * k);
+    cv.add(&cpart, (size_t)nb).add(&spart, (size_t)nb).add(&sums, 2);
+    CHK(cv.commit(c, c->alloc_rows));
+  }
+  if (!W_hat) {
+    CHK(run_phase2(c, nullptr, nullptr, nullptr, W, nullptr));
+    W_hat = W;
+  }
+  launch_coh_sep(c->st, W_hat, n, k, c->labels, cpart, spart);
+  launch_mean(c->st, cpart, nb, 1, sums);
+  launch_mean(c->st, spart, nb, 1, sums + 1);
+  HIPCHK(hipGetLastError());
+  double h[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  // denominators: unordered pairs inside clusters, and across clusters
+  int64_t pin = 0, pout = 0, before = 0;
+  for (int j = 0; j < k; ++j) {
+    const int64_t cj = c->csize_h[j];
+    pin += cj * (cj - 1) / 2;
+    pout += cj * ((int64_t)n - before - cj);
+    before += cj;
+  }
+  *coh_host = pin > 0 ? 0.5 * h[0] / (double)pin : 0.0;
+  *sep_host = pout > 0 ? h[1] / (double)pout : 0.0;
+  return SILH_OK;
+}
+
 silh_status silh_sample_view(silh_ctx* c, silh_sample_info* out) {
   if (!c || !out) return fail(SILH_E_ARG, "ctx or out is NULL");
   if (c->state != 1) return fail(SILH_E_STATE, "silh_sample_view before a successful silh_pps_sample");

@@ -97,6 +97,14 @@ bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Ar
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
 
+// ---- cohesion / separation numerators from W_hat [n][k] ---------------------
+constexpr int kCohSepMaxBlocks = 1024;
+int coh_sep_blocks(int n);
+// cpart/spart[block] = float64 partial sums of W_hat[e][own(e)] and of
+// W_hat[e][j] over j > own(e)
+void launch_coh_sep(hipStream_t st, const float* W, int n, int k, const int32_t* labels, double* cpart,
+                    double* spart);
+
 // ---- subsampled global estimators (row subsets) ------------------------------
 // rows[i] = floor(B_i * n / 2^53), B_i the 53 Philox bits of counter i in the
 // row stream

@@ -59,6 +59,8 @@ SIGNATURES = {
     "silh_exact_rows": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "silh_coh_sep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
     "silh_sample_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SilhSampleInfo)]),
     "silh_philox_uniform": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -354,6 +356,17 @@ def silh_exact_rows(X, labels, k, rows, metric="eucl", prec="fp32", stream=None,
     if mean:
         res["mean"] = mv.value
     return res
+
+
+def silh_coh_sep(ctx: Context, W_hat=None):
+    """Estimated cohesion and separation (Appendix B); W_hat from
+    silh_weighted_sums, or None to let the library compute it."""
+    lib = load_library()
+    coh, sep = ctypes.c_double(), ctypes.c_double()
+    wp = ctypes.c_void_p(W_hat.data_ptr()) if W_hat is not None else ctypes.c_void_p()
+    with ctx.target():
+        _check(lib.silh_coh_sep(ctx.ptr, wp, ctypes.byref(coh), ctypes.byref(sep)), "silh_coh_sep")
+    return {"coh": coh.value, "sep": sep.value}
 
 
 def gl_s(X, labels, k, m, seed, metric="eucl", prec="fp32"):

@@ -84,6 +84,7 @@ def test_null_arguments():
     p.n = 1
     assert lib.silh_exact(ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8), None,
                           None, None, None, None) == 1
+    assert lib.silh_coh_sep(None, None, None, None) == 1
     lib.silh_destroy(None)   # no-op
 
 

@@ -117,3 +117,50 @@ def test_hoeffding_size_bounds_the_subsampling_error():
         rows = oracle.draw_rows(rs, 3000, m)
         miss += abs(full["s"][rows].mean() - full["mean"]) > eps2
     assert miss <= 0.1 * 200
+
+
+def brute_coh_sep(X, L, k):
+    """Appendix B's definitions over explicit pairs (independent of W)."""
+    n = X.shape[0]
+    intra = inter = 0.0
+    n_intra = n_inter = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            dv = math.sqrt(sum((float(X[i, c]) - float(X[j, c])) ** 2 for c in range(X.shape[1])))
+            if L[i] == L[j]:
+                intra += dv
+                n_intra += 1
+            else:
+                inter += dv
+                n_inter += 1
+    return intra / n_intra, inter / n_inter
+
+
+def test_coh_sep_from_exact_weights_matches_pair_definitions():
+    X, L = synth.tiny_case(90, 3, 4, seed=14)
+    ex = oracle.exact(X, L, 4, "eucl")
+    cs = oracle.coh_sep_from_weights(ex["W"], L, ex["sizes"])
+    coh, sep = brute_coh_sep(X, L, 4)
+    assert abs(cs["coh"] - coh) < 1e-12 * coh
+    assert abs(cs["sep"] - sep) < 1e-12 * sep
+    sizes = np.bincount(L, minlength=4)
+    assert cs["coh_den"] == sum(c * (c - 1) // 2 for c in sizes)
+    assert cs["sep_den"] == (90 * 90 - (sizes ** 2).sum()) // 2
+
+
+def test_coh_sep_estimates_are_unbiased_in_the_numerators():
+    """E[W_hat] = W (Horvitz-Thompson), so the numerators of the estimates are
+    unbiased; z-test over 300 seeds."""
+    X, L = synth.tiny_case(600, 4, 3, seed=15)
+    ex = oracle.exact(X, L, 3, "eucl")
+    truth = oracle.coh_sep_from_weights(ex["W"], L, ex["sizes"])
+    vals = []
+    for seed in range(300):
+        smp = oracle.sample(X, L, 3, "eucl", 24, 0.01, seed, "pps")
+        est = oracle.estimate(X, L, 3, "eucl", smp)
+        cs = oracle.coh_sep_from_weights(est["W"], L, smp["sizes"])
+        vals.append((cs["coh"], cs["sep"]))
+    vals = np.array(vals)
+    for c, key in ((0, "coh"), (1, "sep")):
+        se = vals[:, c].std() / math.sqrt(len(vals))
+        assert abs(vals[:, c].mean() - truth[key]) < 5 * se + 1e-12
