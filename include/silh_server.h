@@ -1,0 +1,95 @@
+/*
+ * silh_server.h - a request-serving runtime around the sampled-silhouette
+ * path of include/silh.h, on one GPU.
+ *
+ * Datasets stay resident in device memory (caller-owned).  Each request asks
+ * for the silhouette estimate s_hat_2 of one clustering of one dataset
+ * (Algorithm 1, Phases 1 and 2, and Eq. 9: the sequence silh_sample_init,
+ * silh_pps_sample, silh_scores of silh.h, with the same kernels and results).
+ * Requests are admitted first in, first out while the device memory they are
+ * estimated to need fits the configured budget, and run concurrently on
+ * worker threads, each with its own HIP stream and its own cache of device
+ * blocks (returned to the device only by silh_server_destroy).
+ *
+ * All calls are thread-safe.  Timestamps are nanoseconds of one steady clock
+ * (silh_server_now_ns), so callers can schedule arrivals on the same clock.
+ */
+#ifndef SILH_SERVER_H
+#define SILH_SERVER_H
+
+#include <stdint.h>
+
+#include "silh.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct silh_server silh_server;
+
+typedef struct {
+  int32_t workers;           /* concurrent requests (worker threads / streams), 1..64 */
+  int32_t reserved0;         /* must be 0 */
+  uint64_t hbm_budget_bytes; /* device memory the in-flight requests may use (estimate) */
+} silh_server_cfg;
+
+typedef struct {
+  int32_t dataset;        /* id from silh_server_add_dataset */
+  int32_t k;              /* number of cluster ids, 2..4096 */
+  const int32_t* labels;  /* [n] int32 in [0, k), device; caller-owned and unchanged
+                             until the request has completed */
+  int32_t metric;         /* silh_metric */
+  int32_t prec;           /* silh_prec (as silh_params.prec) */
+  int32_t sampler;        /* silh_sampler */
+  int32_t reserved0;      /* must be 0 */
+  int64_t t;              /* expected samples per cluster (>= 1) */
+  double delta;           /* in (0, 1) */
+  uint64_t seed;          /* Philox key */
+} silh_request;
+
+typedef struct {
+  int32_t status;         /* silh_status of the request */
+  int32_t reserved0;
+  double s_mean;          /* s_hat_2 (Eq. 9) when status is SILH_OK */
+  int64_t S;              /* sampled elements */
+  int64_t submit_ns;      /* silh_server_submit returned the ticket */
+  int64_t start_ns;       /* a worker began the request */
+  int64_t done_ns;        /* the result was ready */
+  char message[160];      /* silh_last_error text of a failed request */
+} silh_result;
+
+/* Steady-clock time in nanoseconds (the clock of every silh_result). */
+int64_t silh_server_now_ns(void);
+
+/* Create a server on the calling thread's current device.  SILH_E_ARG for
+ * NULL arguments, workers outside [1, 64], reserved0 != 0 or a zero budget. */
+silh_status silh_server_create(const silh_server_cfg* cfg, silh_server** out);
+
+/* Register a resident dataset: X [n][d] float32 row-major, device,
+ * caller-owned and unchanged while any request on it may run.  *id receives
+ * its id.  SILH_E_ARG for NULL X or id, n outside [2, 2^30], d outside
+ * [1, 256]. */
+silh_status silh_server_add_dataset(silh_server* srv, const float* X, int64_t n, int32_t d, int32_t* id);
+
+/* Queue a request; *ticket receives its id.  Arguments are checked as
+ * silh_sample_init checks them (SILH_E_ARG / SILH_E_UNSUPPORTED) before the
+ * request is queued; SILH_E_NOMEM if its estimate alone exceeds the budget. */
+silh_status silh_server_submit(silh_server* srv, const silh_request* req, int64_t* ticket);
+
+/* Block until the request has completed, copy its result to *out and retire
+ * the ticket.  SILH_E_ARG for an unknown (or already retired) ticket. */
+silh_status silh_server_wait(silh_server* srv, int64_t ticket, silh_result* out);
+
+/* Block until every queued request has completed (results stay available to
+ * silh_server_wait). */
+silh_status silh_server_drain(silh_server* srv);
+
+/* Drain, stop the workers, free their cached device blocks and streams.
+ * NULL is a no-op. */
+void silh_server_destroy(silh_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SILH_SERVER_H */

@@ -22,6 +22,7 @@ ARCH = os.environ.get("SILH_OFFLOAD_ARCH", "gfx950")
 SOURCES = {
     # file: extra flags
     "silh_api.cpp": [],
+    "silh_server.cpp": [],
     "k_index.hip": [],
     "k_phase1.hip": ["-ffp-contract=off"],
     "k_phase2_valu.hip": [],

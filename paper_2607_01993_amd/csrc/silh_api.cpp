@@ -700,6 +700,13 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
 
 }  // namespace
 
+namespace silh {
+silh_status validate_params(const silh_params* prm, const float* X, const int32_t* labels, int64_t* t) {
+  return check_params(prm, X, labels, false, t);
+}
+int dm_for(int d) { return phase2_valu_dm(d); }
+}  // namespace silh
+
 extern "C" {
 
 silh_status silh_sample_init(const silh_params* prm, const float* X, const int32_t* labels,

@@ -97,6 +97,15 @@ bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Ar
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
 
+// ---- host-side helpers shared by the C-ABI files ----------------------------
+}  // namespace silh
+#include "../../include/silh.h"
+namespace silh {
+// the argument checks of silh_sample_init; *t receives the sample size used
+silh_status validate_params(const silh_params* prm, const float* X, const int32_t* labels, int64_t* t);
+// padded row width of the packed sample for dimension d (0 if unsupported)
+int dm_for(int d);
+
 // ---- cohesion / separation numerators from W_hat [n][k] ---------------------
 constexpr int kCohSepMaxBlocks = 1024;
 int coh_sep_blocks(int n);

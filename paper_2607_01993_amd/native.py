@@ -39,7 +39,24 @@ class SilhSampleInfo(ctypes.Structure):
                 ("f0_offsets_host", ctypes.POINTER(ctypes.c_int64)), ("t", ctypes.c_int64)]
 
 
-# name -> (restype, argtypes), exactly the symbols of include/silh.h
+class SilhServerCfg(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class SilhRequest(ctypes.Structure):
+    _fields_ = [("dataset", ctypes.c_int32), ("k", ctypes.c_int32), ("labels", ctypes.c_void_p),
+                ("metric", ctypes.c_int32), ("prec", ctypes.c_int32), ("sampler", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("t", ctypes.c_int64), ("delta", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class SilhResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("s_mean", ctypes.c_double),
+                ("S", ctypes.c_int64), ("submit_ns", ctypes.c_int64), ("start_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("message", ctypes.c_char * 160)]
+
+
+# name -> (restype, argtypes), exactly the symbols of include/*.h
 SIGNATURES = {
     "silh_sample_init": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -70,6 +87,15 @@ SIGNATURES = {
     "silh_prof_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "silh_destroy": (None, [ctypes.c_void_p]),
+    "silh_server_now_ns": (ctypes.c_int64, []),
+    "silh_server_create": (ctypes.c_int, [ctypes.POINTER(SilhServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
+    "silh_server_add_dataset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32)]),
+    "silh_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SilhRequest),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "silh_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(SilhResult)]),
+    "silh_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
+    "silh_server_destroy": (None, [ctypes.c_void_p]),
     "silh_last_error": (ctypes.c_char_p, []),
     "silh_version": (ctypes.c_char_p, []),
 }
@@ -465,3 +491,73 @@ def silh_destroy(ctx: Context):
 
 def version() -> str:
     return load_library().silh_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# serving runtime (include/silh_server.h)
+# ---------------------------------------------------------------------------
+class Server:
+    """Resident datasets, a request queue with a device-memory budget, and
+    worker threads with their own streams (all in the HIP library)."""
+
+    def __init__(self, workers=4, hbm_budget_bytes=64 << 30):
+        _torch()
+        lib = load_library()
+        cfg = SilhServerCfg(int(workers), 0, int(hbm_budget_bytes))
+        out = ctypes.c_void_p()
+        _check(lib.silh_server_create(ctypes.byref(cfg), ctypes.byref(out)), "silh_server_create")
+        self.ptr = out
+        self._keep = {}       # device tensors that must outlive the requests using them
+        self._datasets = []
+
+    def add_dataset(self, X):
+        torch = _torch()
+        if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+            raise ValueError("X must be a contiguous float32 [n, d] device tensor")
+        did = ctypes.c_int32()
+        _check(load_library().silh_server_add_dataset(self.ptr, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                                      X.shape[1], ctypes.byref(did)), "silh_server_add_dataset")
+        self._datasets.append(X)
+        return int(did.value)
+
+    def submit(self, dataset, labels, k, metric="eucl", prec="bf16", sampler="pps", t=256, delta=0.01, seed=0):
+        torch = _torch()
+        if not labels.is_cuda or labels.dtype != torch.int32 or not labels.is_contiguous():
+            raise ValueError("labels must be a contiguous int32 device tensor")
+        req = SilhRequest(int(dataset), int(k), ctypes.c_void_p(labels.data_ptr()),
+                          METRICS[metric] if isinstance(metric, str) else int(metric),
+                          PRECS[prec] if isinstance(prec, str) else int(prec),
+                          SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler), 0, int(t),
+                          float(delta), int(seed) & 0xFFFFFFFFFFFFFFFF)
+        tk = ctypes.c_int64()
+        _check(load_library().silh_server_submit(self.ptr, ctypes.byref(req), ctypes.byref(tk)),
+               "silh_server_submit")
+        self._keep[int(tk.value)] = labels
+        return int(tk.value)
+
+    def wait(self, ticket):
+        res = SilhResult()
+        _check(load_library().silh_server_wait(self.ptr, int(ticket), ctypes.byref(res)), "silh_server_wait")
+        self._keep.pop(int(ticket), None)
+        return {"status": STATUS.get(res.status, res.status), "s_mean": res.s_mean, "S": int(res.S),
+                "submit_ns": int(res.submit_ns), "start_ns": int(res.start_ns), "done_ns": int(res.done_ns),
+                "message": res.message.decode(errors="replace")}
+
+    def drain(self):
+        _check(load_library().silh_server_drain(self.ptr), "silh_server_drain")
+
+    @staticmethod
+    def now_ns():
+        return int(load_library().silh_server_now_ns())
+
+    def close(self):
+        if self.ptr:
+            load_library().silh_server_destroy(self.ptr)
+            self.ptr = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,10 +12,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    with open(os.path.join(ROOT, "include", "silh.h")) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return set(re.findall(r"\b(silh_[a-z_0-9]+)\s*\(", text))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        with open(os.path.join(ROOT, "include", h)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(silh_[a-z_0-9]+)\s*\(", text))
+    return names
 
 
 def test_header_and_binding_agree():
@@ -118,3 +123,24 @@ def test_rows_calls_reject_bad_arguments():
     p = native._params(10, 4, 3, 0, 0, 0, 1, 0.0, 0.5, 0, use_torch_alloc=False)
     p.k = 1
     assert lib.silh_exact_rows(ctypes.byref(p), fake, fake, fake, 5, None, None, None, None, None) == 1
+
+
+def test_server_layouts_and_argument_checks():
+    P = native
+    assert ctypes.sizeof(P.SilhServerCfg) == 16
+    assert ctypes.sizeof(P.SilhRequest) == 56 and P.SilhRequest.t.offset == 32
+    assert ctypes.sizeof(P.SilhResult) == 48 + 160
+    lib = native.load_library()
+    out = ctypes.c_void_p()
+    for w, r, b in ((0, 0, 1 << 30), (65, 0, 1 << 30), (2, 1, 1 << 30), (2, 0, 0)):
+        cfg = P.SilhServerCfg(w, r, b)
+        assert lib.silh_server_create(ctypes.byref(cfg), ctypes.byref(out)) == 1
+        assert not out.value
+    assert lib.silh_server_create(None, ctypes.byref(out)) == 1
+    assert lib.silh_server_submit(None, None, None) == 1
+    assert lib.silh_server_wait(None, 1, None) == 1
+    assert lib.silh_server_drain(None) == 1
+    assert lib.silh_server_add_dataset(None, None, 10, 4, None) == 1
+    lib.silh_server_destroy(None)
+    t0 = lib.silh_server_now_ns()
+    assert lib.silh_server_now_ns() >= t0 > 0
