@@ -147,3 +147,111 @@ def tiny_case(n: int, d: int, k: int, seed: int, sigma=(0.5, 2.0), sizes=None):
         sizes = np.maximum(1, np.floor(n * w / w.sum()).astype(np.int64))
         sizes[0] += n - int(sizes.sum())
     return gaussian_blobs(n, d, k, seed=seed, sizes=sizes, sigma=sigma)
+
+
+# ---------------------------------------------------------------------------
+# Exponential blobs and Voronoi clusterings (the k-sweep workload), and the
+# serving workload's dataset pool and request stream.
+# ---------------------------------------------------------------------------
+def exp_blobs(n: int, d: int, blobs: int, seed: int, offset_range=(0.0, 10.0)):
+    """x = o_b + Exp(1) per coordinate, o_b ~ U[offset_range]^d, each row in
+    one of `blobs` blobs chosen uniformly (positive data, for Canberra)."""
+    rng = np.random.default_rng(seed)
+    offs = rng.uniform(offset_range[0], offset_range[1], size=(blobs, d))
+    which = rng.integers(0, blobs, size=n)
+    X = offs[which] + rng.exponential(1.0, size=(n, d))
+    return np.ascontiguousarray(X.astype(np.float32))
+
+
+def voronoi_centers(n: int, k: int, seed) -> np.ndarray:
+    """k distinct row indices drawn with the given seed (an int or a tuple)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=k, replace=False))
+
+
+def voronoi_labels(X, centers, chunk: int = 1 << 16):
+    """Nearest center by Euclidean distance (ties to the lowest index), on the
+    host in float64; X [n][d], centers: row indices."""
+    X = np.asarray(X, dtype=np.float64)
+    C = X[np.asarray(centers)]
+    cn = (C * C).sum(axis=1)
+    out = np.empty(X.shape[0], dtype=np.int32)
+    for r0 in range(0, X.shape[0], chunk):
+        xb = X[r0:r0 + chunk]
+        d2 = (xb * xb).sum(axis=1)[:, None] - 2.0 * xb @ C.T + cn[None, :]
+        out[r0:r0 + chunk] = np.argmin(d2, axis=1)
+    return out
+
+
+def voronoi_labels_device(X, centers, chunk: int = 1 << 18):
+    """The same clustering rule on a device tensor X (float32 arithmetic;
+    used for large inputs that are only checked against themselves)."""
+    import torch
+    C = X[torch.as_tensor(np.asarray(centers), device=X.device, dtype=torch.long)]
+    cn = (C * C).sum(dim=1)
+    out = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    for r0 in range(0, X.shape[0], chunk):
+        xb = X[r0:r0 + chunk]
+        d2 = (xb * xb).sum(dim=1, keepdim=True) - 2.0 * (xb @ C.T) + cn[None, :]
+        out[r0:r0 + chunk] = torch.argmin(d2, dim=1).to(torch.int32)
+    return out
+
+
+def config_sweep(n: int = 500_000, d: int = 64, blobs: int = 16, seed: int = 3):
+    """k-sweep data: exponential blobs (their Voronoi clusterings for
+    k = 2..257 come from voronoi_centers(n, k, (seed, k)))."""
+    return exp_blobs(n, d, blobs, seed)
+
+
+SERVING_METRICS = ("eucl", "cos", "manh", "canb")
+
+
+def serving_pool_specs(count: int = 32, seed: int = 5, dims=(16, 64, 128), n_range=(1e4, 2e6)):
+    """The resident datasets of the serving workload: n = round(10^U[log10
+    n_range]), d from dims, a metric each (its data family follows it)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(round(10.0 ** rng.uniform(np.log10(n_range[0]), np.log10(n_range[1]))))
+        specs.append({"id": i, "n": n, "d": int(rng.choice(dims)),
+                      "metric": SERVING_METRICS[int(rng.integers(0, 4))], "seed": 100 + i})
+    return specs
+
+
+def serving_dataset(spec, device):
+    """Generate one serving dataset on the device (torch generator, seeded):
+    Zipf Gaussian blobs (Euclidean / Manhattan; rows scaled to unit length for
+    cosine) or exponential blobs (Canberra)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(spec["seed"]))
+    n, d = spec["n"], spec["d"]
+    if spec["metric"] == "canb":
+        offs = torch.rand((16, d), generator=g, device=device) * 10.0
+        which = torch.randint(0, 16, (n,), generator=g, device=device)
+        X = offs[which] + torch.empty((n, d), device=device).exponential_(1.0, generator=g)
+        return X.contiguous()
+    k = 16
+    sizes = torch.as_tensor(zipf_sizes(n, k), device=device)
+    centers = torch.rand((k, d), generator=g, device=device) * 20.0 - 10.0
+    sig = torch.rand((k,), generator=g, device=device) * 1.5 + 0.5
+    lab = torch.repeat_interleave(torch.arange(k, device=device), sizes)
+    X = centers[lab] + sig[lab, None] * torch.randn((n, d), generator=g, device=device)
+    X = X[torch.randperm(n, generator=g, device=device)]
+    if spec["metric"] == "cos":
+        X = X / X.norm(dim=1, keepdim=True).clamp_min(1e-30)
+    return X.contiguous()
+
+
+def serving_requests(specs, count: int, seed: int = 7, ks=(2, 128), ts=(64, 256, 1024)):
+    """Request stream: dataset uniform, k ~ U{ks}, t from ts, Philox seed
+    1000 + request id; the clustering is the Voronoi partition of k rows
+    drawn with seed (request seed, k)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        spec = specs[int(rng.integers(0, len(specs)))]
+        k = int(rng.integers(ks[0], ks[1] + 1))
+        reqs.append({"id": i, "dataset": spec["id"], "k": k, "t": int(rng.choice(ts)), "seed": 1000 + i,
+                     "centers_seed": (1000 + i, k)})
+    return reqs
