@@ -6,6 +6,8 @@
  * for the silhouette estimate s_hat_2 of one clustering of one dataset
  * (Algorithm 1, Phases 1 and 2, and Eq. 9: the sequence silh_sample_init,
  * silh_pps_sample, silh_scores of silh.h, with the same kernels and results).
+ * A request may instead ask for the subsampled estimate of Eq. 10 (silh.h's
+ * silh_draw_rows and silh_scores_rows).
  * Requests are admitted first in, first out while the device memory they are
  * estimated to need fits the configured budget, and run concurrently on
  * worker threads, each with its own HIP stream and its own cache of device
@@ -45,6 +47,9 @@ typedef struct {
   int64_t t;              /* expected samples per cluster (>= 1) */
   double delta;           /* in (0, 1) */
   uint64_t seed;          /* Philox key */
+  int64_t m;              /* 0: the mean over every element (Eq. 9, gl-pps-f);
+                             m > 0: the mean over m uniform row draws with the
+                             same seed (Eq. 10, gl-pps-s / gl-uni-s) */
 } silh_request;
 
 typedef struct {
@@ -72,8 +77,9 @@ silh_status silh_server_create(const silh_server_cfg* cfg, silh_server** out);
 silh_status silh_server_add_dataset(silh_server* srv, const float* X, int64_t n, int32_t d, int32_t* id);
 
 /* Queue a request; *ticket receives its id.  Arguments are checked as
- * silh_sample_init checks them (SILH_E_ARG / SILH_E_UNSUPPORTED) before the
- * request is queued; SILH_E_NOMEM if its estimate alone exceeds the budget. */
+ * silh_sample_init checks them (SILH_E_ARG / SILH_E_UNSUPPORTED; also m
+ * outside [0, 2^30]) before the request is queued; SILH_E_NOMEM if its
+ * estimate alone exceeds the budget. */
 silh_status silh_server_submit(silh_server* srv, const silh_request* req, int64_t* ticket);
 
 /* Block until the request has completed, copy its result to *out and retire
@@ -87,6 +93,27 @@ silh_status silh_server_drain(silh_server* srv);
 /* Drain, stop the workers, free their cached device blocks and streams.
  * NULL is a no-op. */
 void silh_server_destroy(silh_server* srv);
+
+/*
+ * silh_sweep - s_hat_2 (Algorithm 1 and Eq. 9; with m > 0 the subsampled
+ * mean of Eq. 10 over m row draws) of K clusterings of one dataset, and the
+ * clustering with the largest value (the choice of k by the global
+ * silhouette, Section 5, "Selection of the best value of k").  Clustering i has labels[i*n .. i*n + n) in
+ * [0, ks[i]); every other setting (metric, prec, sampler, t, delta, seed, the
+ * allocator hooks are ignored) comes from *base, whose k is ignored.  The
+ * clusterings run concurrently on `workers` worker streams (1..64) through
+ * the serving runtime, within hbm_budget_bytes of estimated device memory.
+ *  X        [n][d] float32, device;  labels  [K][n] int32, device (caller-owned)
+ *  ks       [K] int32, host;  means_host  [K] float64, host
+ *  best_host  index of the largest mean (the lowest index among equal ones),
+ *           nullable
+ * The caller's stream is synchronised first (X and labels must be ready on
+ * it); the call returns when every clustering is done.  The first failing
+ * clustering's status is returned (its mean is NaN); the others still run.
+ */
+silh_status silh_sweep(const silh_params* base, const float* X, const int32_t* labels, const int32_t* ks,
+                       int32_t K, int64_t m, int32_t workers, uint64_t hbm_budget_bytes, silh_stream stream,
+                       double* means_host, int32_t* best_host);
 
 #ifdef __cplusplus
 }

@@ -21,5 +21,5 @@ from .distance import CANB, COS, EUCL, MANH, dist_matrix, dist_to_point, metric_
 from .philox import STREAM_F0, STREAM_PPS, STREAM_ROWS, STREAM_UNI, bits53, philox4x32_10, uniform53  # noqa: F401
 from .silhouette import (cluster_members, default_t, estimate, exact, global_mean,  # noqa: F401
                          pps_silhouette, sample, scores_from_weights)
-from .global_est import draw_rows, gl_pps_s, gl_s, m_for, subset_mean  # noqa: F401
+from .global_est import draw_rows, gl_pps_s, gl_s, m_for, subset_mean, sweep  # noqa: F401
 from .coh_sep import coh_sep_from_weights  # noqa: F401

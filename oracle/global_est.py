@@ -62,3 +62,21 @@ def gl_pps_s(X, labels, k: int, metric, t: int, delta: float, seed: int, m: int,
     est["mean"] = subset_mean(est["s"])
     est["sample"] = smp
     return est
+
+
+def sweep(X, label_sets, ks, metric, t: int, delta: float, seed: int, m: int = 0, sampler: str = "pps") -> dict:
+    """The choice of k by the global silhouette (Section 5, selection of the
+    best value of k): for each clustering, s_hat_2 (Eq. 9) or, with m > 0,
+    the Eq. 10 mean over m row draws (row seed = seed); the index of the
+    largest (the first among equal ones)."""
+    means = []
+    n = np.asarray(X).shape[0]
+    for L, k in zip(label_sets, ks):
+        smp = sample(X, L, k, metric, t, delta, seed, sampler)
+        if m > 0:
+            est = estimate(X, L, k, metric, smp, rows=draw_rows(seed, n, m))
+            means.append(subset_mean(est["s"]))
+        else:
+            means.append(estimate(X, L, k, metric, smp)["mean"])
+    means = np.array(means)
+    return {"means": means, "best": int(np.argmax(means))}

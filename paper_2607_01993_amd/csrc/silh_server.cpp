@@ -123,7 +123,8 @@ uint64_t estimate_bytes(const Dataset& ds, const silh_request& r) {
   const int mprec = r.prec == SILH_BF16 ? 1 : (r.prec == SILH_FP8 ? 2 : 0);
   const uint64_t kp = mfma ? (uint64_t)silh::mfma_kp(mprec, DM) : 0;
   const uint64_t row = (uint64_t)DM * 4 + kp * 4 + 24;
-  return 24 * n + S * row + ((uint64_t)1 << 20);
+  const uint64_t m = r.m > 0 ? (uint64_t)r.m : 0;  // row draws: ids, gathered rows, outputs
+  return 24 * n + S * row + m * ((uint64_t)ds.d * 4 + 32) + ((uint64_t)1 << 20);
 }
 
 void run_job(Dataset ds, const silh_request& r, Pool& pool, hipStream_t st, silh_result& res) {
@@ -145,10 +146,22 @@ void run_job(Dataset ds, const silh_request& r, Pool& pool, hipStream_t st, silh
   silh_status s = silh_sample_init(&p, ds.X, r.labels, (silh_stream)st, &ctx);
   int64_t S = 0;
   double mean = 0.0;
+  int32_t* rows = nullptr;
   if (s == SILH_OK) s = silh_pps_sample(ctx, &S, nullptr);
-  if (s == SILH_OK) s = silh_scores(ctx, nullptr, nullptr, nullptr, &mean);
+  if (s == SILH_OK && r.m > 0) {
+    rows = static_cast<int32_t*>(pool.get((size_t)r.m * sizeof(int32_t)));
+    if (!rows) s = SILH_E_NOMEM;
+    if (s == SILH_OK) s = silh_draw_rows(r.seed, ds.n, r.m, rows, (silh_stream)st);
+    if (s == SILH_OK) s = silh_scores_rows(ctx, rows, r.m, nullptr, nullptr, nullptr, &mean);
+  } else if (s == SILH_OK) {
+    s = silh_scores(ctx, nullptr, nullptr, nullptr, &mean);
+  }
   if (s != SILH_OK) std::snprintf(res.message, sizeof(res.message), "%s", silh_last_error());
-  silh_destroy(ctx);
+  silh_destroy(ctx);  // synchronises the stream: the row buffer is free again
+  if (rows) {
+    (void)hipStreamSynchronize(st);
+    pool.put(rows);
+  }
   res.status = s;
   res.S = S;
   res.s_mean = mean;
@@ -261,7 +274,7 @@ silh_status silh_server_submit(silh_server* srv, const silh_request* req, int64_
   int64_t t = 0;
   silh_status s = silh::validate_params(&p, ds.X, req->labels, &t);
   if (s != SILH_OK) return s;
-  if (req->t < 1) return SILH_E_ARG;
+  if (req->t < 1 || req->m < 0 || req->m > ((int64_t)1 << 30)) return SILH_E_ARG;
   const uint64_t est = estimate_bytes(ds, *req);
   if (est > srv->budget) return SILH_E_NOMEM;
   {
@@ -311,6 +324,57 @@ void silh_server_destroy(silh_server* srv) {
   srv->cv_work.notify_all();
   for (auto& th : srv->workers) th.join();
   delete srv;
+}
+
+silh_status silh_sweep(const silh_params* base, const float* X, const int32_t* labels, const int32_t* ks,
+                       int32_t K, int64_t m, int32_t workers, uint64_t hbm_budget_bytes, silh_stream stream,
+                       double* means_host, int32_t* best_host) {
+  if (!base || !X || !labels || !ks || !means_host || K < 1) return SILH_E_ARG;
+  if (base->n < 2 || base->n > ((int64_t)1 << 30)) return SILH_E_ARG;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SILH_E_HIP;
+  silh_server_cfg cfg{workers, 0, hbm_budget_bytes};
+  silh_server* srv = nullptr;
+  silh_status s = silh_server_create(&cfg, &srv);
+  if (s != SILH_OK) return s;
+  int32_t did = 0;
+  s = silh_server_add_dataset(srv, X, base->n, base->d, &did);
+  std::vector<int64_t> tickets((size_t)K, 0);
+  silh_status first_bad = SILH_OK;
+  for (int32_t i = 0; i < K && s == SILH_OK; ++i) {
+    silh_request r{};
+    r.dataset = did;
+    r.k = ks[i];
+    r.labels = labels + (size_t)i * (size_t)base->n;
+    r.metric = base->metric;
+    r.prec = base->prec;
+    r.sampler = base->sampler;
+    r.t = base->t;
+    r.delta = base->delta;
+    r.seed = base->seed;
+    r.m = m;
+    const silh_status q = silh_server_submit(srv, &r, &tickets[i]);
+    if (q != SILH_OK) {
+      tickets[i] = 0;
+      means_host[i] = __builtin_nan("");
+      if (first_bad == SILH_OK) first_bad = q;
+    }
+  }
+  for (int32_t i = 0; i < K && s == SILH_OK; ++i) {
+    if (tickets[i] == 0) continue;
+    silh_result res{};
+    silh_server_wait(srv, tickets[i], &res);
+    means_host[i] = res.status == SILH_OK ? res.s_mean : __builtin_nan("");
+    if (res.status != SILH_OK && first_bad == SILH_OK) first_bad = (silh_status)res.status;
+  }
+  silh_server_destroy(srv);
+  if (s != SILH_OK) return s;
+  if (best_host) {
+    int32_t best = -1;
+    for (int32_t i = 0; i < K; ++i)
+      if (means_host[i] == means_host[i] && (best < 0 || means_host[i] > means_host[best])) best = i;
+    *best_host = best;
+  }
+  return first_bad;
 }
 
 }  // extern "C"

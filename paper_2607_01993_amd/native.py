@@ -47,7 +47,7 @@ class SilhRequest(ctypes.Structure):
     _fields_ = [("dataset", ctypes.c_int32), ("k", ctypes.c_int32), ("labels", ctypes.c_void_p),
                 ("metric", ctypes.c_int32), ("prec", ctypes.c_int32), ("sampler", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("t", ctypes.c_int64), ("delta", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("m", ctypes.c_int64)]
 
 
 class SilhResult(ctypes.Structure):
@@ -96,6 +96,10 @@ SIGNATURES = {
     "silh_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(SilhResult)]),
     "silh_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
     "silh_server_destroy": (None, [ctypes.c_void_p]),
+    "silh_sweep": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int32)]),
     "silh_last_error": (ctypes.c_char_p, []),
     "silh_version": (ctypes.c_char_p, []),
 }
@@ -493,6 +497,28 @@ def version() -> str:
     return load_library().silh_version().decode()
 
 
+def silh_sweep(X, labels, ks, metric="eucl", prec="bf16", sampler="pps", t=128, delta=0.01, seed=0, m=0,
+               workers=4, hbm_budget_bytes=64 << 30, stream=None):
+    """s_hat_2 (m = 0) or the Eq. 10 mean over m row draws of K clusterings
+    (labels [K, n] int32 device, ks their k) and the index of the best one."""
+    import numpy as np
+    torch = _torch()
+    lib = load_library()
+    if labels.dtype != torch.int32 or labels.dim() != 2 or labels.shape[1] != X.shape[0] \
+            or not labels.is_contiguous() or not labels.is_cuda:
+        raise ValueError("labels must be a contiguous int32 [K, n] device tensor")
+    K = labels.shape[0]
+    ksa = (ctypes.c_int32 * K)(*[int(v) for v in ks])
+    means = (ctypes.c_double * K)()
+    best = ctypes.c_int32()
+    st, sh = _stream_handle(stream)
+    p = _params(X.shape[0], X.shape[1], 2, metric, prec, sampler, t, 0.0, delta, seed, use_torch_alloc=False)
+    _check(lib.silh_sweep(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(labels.data_ptr()), ksa,
+                          K, int(m), int(workers), int(hbm_budget_bytes), sh, means, ctypes.byref(best)),
+           "silh_sweep")
+    return {"means": np.frombuffer(means, dtype=np.float64).copy(), "best": int(best.value)}
+
+
 # ---------------------------------------------------------------------------
 # serving runtime (include/silh_server.h)
 # ---------------------------------------------------------------------------
@@ -520,7 +546,7 @@ class Server:
         self._datasets.append(X)
         return int(did.value)
 
-    def submit(self, dataset, labels, k, metric="eucl", prec="bf16", sampler="pps", t=256, delta=0.01, seed=0):
+    def submit(self, dataset, labels, k, metric="eucl", prec="bf16", sampler="pps", t=256, delta=0.01, seed=0, m=0):
         torch = _torch()
         if not labels.is_cuda or labels.dtype != torch.int32 or not labels.is_contiguous():
             raise ValueError("labels must be a contiguous int32 device tensor")
@@ -528,7 +554,7 @@ class Server:
                           METRICS[metric] if isinstance(metric, str) else int(metric),
                           PRECS[prec] if isinstance(prec, str) else int(prec),
                           SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler), 0, int(t),
-                          float(delta), int(seed) & 0xFFFFFFFFFFFFFFFF)
+                          float(delta), int(seed) & 0xFFFFFFFFFFFFFFFF, int(m))
         tk = ctypes.c_int64()
         _check(load_library().silh_server_submit(self.ptr, ctypes.byref(req), ctypes.byref(tk)),
                "silh_server_submit")

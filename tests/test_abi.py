@@ -128,7 +128,7 @@ def test_rows_calls_reject_bad_arguments():
 def test_server_layouts_and_argument_checks():
     P = native
     assert ctypes.sizeof(P.SilhServerCfg) == 16
-    assert ctypes.sizeof(P.SilhRequest) == 56 and P.SilhRequest.t.offset == 32
+    assert ctypes.sizeof(P.SilhRequest) == 64 and P.SilhRequest.t.offset == 32 and P.SilhRequest.m.offset == 56
     assert ctypes.sizeof(P.SilhResult) == 48 + 160
     lib = native.load_library()
     out = ctypes.c_void_p()

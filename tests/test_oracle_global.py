@@ -164,3 +164,18 @@ def test_coh_sep_estimates_are_unbiased_in_the_numerators():
     for c, key in ((0, "coh"), (1, "sep")):
         se = vals[:, c].std() / math.sqrt(len(vals))
         assert abs(vals[:, c].mean() - truth[key]) < 5 * se + 1e-12
+
+
+def test_sweep_best_matches_the_exact_best():
+    """Voronoi clusterings of blob data: the PPS estimates pick the same
+    clustering as the exact global silhouette (values far apart here:
+    0.61, 0.73, 0.24, 0.26, 0.14), and the subsampled means stay close."""
+    X, L0 = synth.tiny_case(1200, 4, 4, seed=16, sigma=(0.2, 0.4))
+    ks = [2, 3, 4, 5, 6]
+    sets = [synth.voronoi_labels(X, synth.voronoi_centers(1200, k, (16, k))) for k in ks]
+    exact = [oracle.exact(X, L, k, "eucl")["mean"] for L, k in zip(sets, ks)]
+    res = oracle.sweep(X, sets, ks, "eucl", t=64, delta=0.01, seed=1)
+    assert int(np.argmax(exact)) == res["best"]
+    assert np.max(np.abs(res["means"] - np.array(exact))) < 0.05
+    sub = oracle.sweep(X, sets, ks, "eucl", t=64, delta=0.01, seed=1, m=600)
+    assert np.max(np.abs(sub["means"] - res["means"])) < 0.1
