@@ -238,6 +238,23 @@ silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_
  */
 silh_status silh_coh_sep(silh_ctx* ctx, const float* W_hat, double* coh_host, double* sep_host);
 
+/*
+ * Autotuning of the matrix-core Phase-2 kernel's block shape (one or two
+ * 32-element blocks per wave), process-wide:
+ *  mode 0  the built-in choice (two for float32 operands with d <= 32);
+ *  mode 1  (default) on the first launch for a key (metric, operand type, d
+ *          rounded up as in the kernels, floor(log2) of the padded sample
+ *          size) time both shapes once, keep the faster; setting mode 1
+ *          again forgets the measurements;
+ *  mode 2 / 3  always one / two.
+ * Results do not depend on the shape (the partial sums of the mean are per
+ * 128 elements, added in the same order, in every shape).  SILH_E_ARG for a mode outside [0, 3].
+ */
+silh_status silh_set_tuning(int mode);
+
+/* *pb = the measured shape for that key (1 or 2), 0 if none yet. */
+silh_status silh_tuning_choice(int metric, int prec, int d, int64_t S_pad, int* pb);
+
 /* Read-only view of a context's Phase-1 result (for inspection and tests). */
 typedef struct {
   int64_t S;                  /* sum_j |F_j|                                              */

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   constexpr int AUG0 = DM - C::HALF;
   static_assert(C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
   constexpr float S2 = kFp8Scale * kFp8Scale;
-  __shared__ double sh[4];
+  __shared__ double sh32[4 * PB];  // 32-element partials of the block, in element order
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int col = lane & 31;
@@ -639,7 +639,6 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       }
     }
   }
-  double ssum = 0.0;
 #pragma unroll
   for (int b = 0; b < PB; ++b) {
     const int szo = csize[own[b]];
@@ -652,30 +651,48 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       if (a_out) a_out[pout[b]] = (float)a;
       if (b_out) b_out[pout[b]] = (float)bb;
       if (s_out) s_out[pout[b]] = (float)s;
-      ssum += s;
     }
+    // a float64 partial per 32 elements (fixed tree over the wave) ...
+    const double part = wave_sum_f64(writer ? s : 0.0);
+    if (lane == 0) sh32[(threadIdx.x >> 6) * PB + b] = part;
   }
-  const double tot = block_sum_f64<256>(ssum, sh);
-  if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
+  // ... and per 128 elements the four of them added in element order, so the
+  // partials, and the mean, do not depend on the block shape PB
+  __syncthreads();
+  if (threadIdx.x < PB) {
+    const int g = threadIdx.x;
+    const int row0 = blockIdx.x * 128 * PB + 128 * g;
+    const double v = ((sh32[4 * g] + sh32[4 * g + 1]) + sh32[4 * g + 2]) + sh32[4 * g + 3];
+    if (row0 < n) bpart[row0 >> 7] = v;
+  }
 }
 
-// elements per block of the MFMA kernel (4 waves x 32 x PB)
-// float32 is bound by the MFMA rate: two blocks per wave halve the B-operand
-// traffic per pair.  bf16 keeps one block (four waves per SIMD hide latency
-// better than the second block saves).
-template <int P, int DM>
-constexpr int mfma_pb() {
-  return (P == 0 && DM <= 32) ? 2 : 1;
-}
+// 32-element blocks per wave (PB): two halve the B-operand loads per pair
+// (the float32 path is bound by the MFMA rate and gains) but double the
+// accumulator and A-operand registers (fewer waves per SIMD).  The default
+// below is the measured choice on the benchmark workload; the autotuner may
+// pick per (metric, operands, d, sample size).  fp8 always uses one.
+int mfma_pb_default(int prec, int DM) { return (prec == 0 && DM <= 32) ? 2 : 1; }
 
-template <int M, int P, int DM>
-static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
-                            const float* bnorm) {
-  constexpr int PB = mfma_pb<P, DM>();
+template <int M, int P, int DM, int PB>
+static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
+                           const float* bnorm) {
   const int blocks = (int)ceil_div(A.n, 128 * PB);
   hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
                      A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart,
                      bnorm);
+}
+
+template <int M, int P, int DM>
+static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
+                            const float* bnorm, int pb) {
+  if constexpr (P != 2) {
+    if (pb == 2) {
+      launch_mfma_pb<M, P, DM, 2>(st, A, mu, Ym, bnorm);
+      return;
+    }
+  }
+  launch_mfma_pb<M, P, DM, 1>(st, A, mu, Ym, bnorm);
 }
 
 template <int M, int P, int DM>
@@ -739,12 +756,10 @@ bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float*
 }
 
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
-                        const void* Ym, const float* bnorm) {
-  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym, bnorm);
+                        const void* Ym, const float* bnorm, int pb) {
+  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym, bnorm, pb);
 }
 
-int phase2_mfma_rows(int prec, int DM) {
-  return 128 * ((prec == 0 && DM <= 32) ? 2 : 1);
-}
+int phase2_mfma_rows(int, int) { return 128; }
 
 }  // namespace silh

@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -579,6 +581,62 @@ silh_status phase1(silh_ctx* c) {
   return compact_and_pack(c);
 }
 
+// ---- autotuning of the MFMA Phase-2 block shape ------------------------------
+// Key: (metric, operand type, padded row width, floor(log2(padded sample
+// size))).  On the first Phase-2 launch of a key both shapes run once on the
+// context's stream, timed with events, and the faster is kept for the
+// process.  Every shape writes the same values (each element's arithmetic
+// and the 128-element partials of the mean do not depend on it).
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, int> g_tune;
+std::atomic<int> g_tune_mode{1};
+
+int size_bucket(int64_t S_pad) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << (b + 1)) <= S_pad) ++b;
+  return b;
+}
+
+int pick_pb(silh_ctx* c, const P2Args& A) {
+  if (c->mprec == 2) return 1;
+  const int mode = g_tune_mode.load();
+  if (mode == 0) return mfma_pb_default(c->mprec, c->DM);
+  if (mode == 2 || mode == 3) return mode - 1;
+  const std::array<int, 4> key{c->prm.metric, c->mprec, c->DM, size_bucket(c->S_pad)};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  bool ok = true;
+  for (auto& ev : e) ok = ok && hipEventCreate(&ev) == hipSuccess;
+  float t1 = 0.f, t2 = 0.f;
+  if (ok) {
+    ok = hipEventRecord(e[0], c->st) == hipSuccess &&
+         launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym, c->bnorm, 1) &&
+         hipEventRecord(e[1], c->st) == hipSuccess &&
+         launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym, c->bnorm, 2) &&
+         hipEventRecord(e[2], c->st) == hipSuccess && hipEventSynchronize(e[2]) == hipSuccess &&
+         hipEventElapsedTime(&t1, e[0], e[1]) == hipSuccess && hipEventElapsedTime(&t2, e[1], e[2]) == hipSuccess;
+  }
+  for (auto& ev : e)
+    if (ev) (void)hipEventDestroy(ev);
+  if (!ok) {
+    (void)hipGetLastError();
+    return mfma_pb_default(c->mprec, c->DM);
+  }
+  const int choice = t2 < t1 ? 2 : 1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.emplace(key, choice);
+  return choice;
+}
+
+bool launch_p2(silh_ctx* c, const P2Args& A, int pb) {
+  if (!c->mfma) return launch_phase2_valu(c->st, c->prm.metric, c->DM, A);
+  return launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym, c->bnorm, pb);
+}
+
 silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, double* mean_host) {
   P2Args A;
   A.X = c->X;
@@ -599,10 +657,9 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
   A.What = What;
   A.bpart = c->bpart;
   {
+    const int pb = c->mfma ? pick_pb(c, A) : 0;  // (tuning runs stay outside the timed launch)
     Launch L(c, K_PHASE2);
-    const bool ok = c->mfma ? launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym,
-                                                 c->bnorm)
-                            : launch_phase2_valu(c->st, c->prm.metric, c->DM, A);
+    const bool ok = launch_p2(c, A, pb);
     if (!ok) return fail(SILH_E_UNSUPPORTED, "no Phase-2 kernel for metric %d, d=%d", c->prm.metric, c->d);
     CHK(L.done());
   }
@@ -679,10 +736,9 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   A.What = nullptr;
   A.bpart = bpu;
   {
+    const int pb = c->mfma ? pick_pb(c, A) : 0;  // (tuning runs stay outside the timed launch)
     Launch L(c, K_PHASE2);
-    const bool ok = c->mfma ? launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym,
-                                                 c->bnorm)
-                            : launch_phase2_valu(c->st, c->prm.metric, c->DM, A);
+    const bool ok = launch_p2(c, A, pb);
     if (!ok) return fail(SILH_E_UNSUPPORTED, "no Phase-2 kernel for metric %d, d=%d", c->prm.metric, c->d);
     CHK(L.done());
   }
@@ -841,6 +897,26 @@ silh_status silh_coh_sep(silh_ctx* c, const float* W_hat, double* coh_host, doub
   }
   *coh_host = pin > 0 ? 0.5 * h[0] / (double)pin : 0.0;
   *sep_host = pout > 0 ? h[1] / (double)pout : 0.0;
+  return SILH_OK;
+}
+
+silh_status silh_set_tuning(int mode) {
+  if (mode < 0 || mode > 3) return fail(SILH_E_ARG, "tuning mode %d outside [0, 3]", mode);
+  g_tune_mode.store(mode);
+  if (mode == 1) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+  }
+  return SILH_OK;
+}
+
+silh_status silh_tuning_choice(int metric, int prec, int d, int64_t S_pad, int* pb) {
+  if (!pb) return fail(SILH_E_ARG, "pb is NULL");
+  const int DM = phase2_valu_dm(d);
+  const int mprec = prec == SILH_BF16 ? 1 : (prec == SILH_FP8 ? 2 : 0);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::array<int, 4>{metric, mprec, DM, size_bucket(S_pad)});
+  *pb = it == g_tune.end() ? 0 : it->second;
   return SILH_OK;
 }
 

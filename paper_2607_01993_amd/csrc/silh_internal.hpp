@@ -89,10 +89,14 @@ void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
                       void* Ym, float* bnorm);
-// elements per 256-thread block of the MFMA Phase-2 kernel
+// elements per float64 partial of the sum of s_hat written by the MFMA
+// Phase-2 kernel (independent of its block shape)
 int phase2_mfma_rows(int prec, int DM);
+// 32-element blocks per wave: the default choice, and the launcher (pb 1 or
+// 2; fp8 always runs with 1)
+int mfma_pb_default(int prec, int DM);
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
-                        const void* Ym, const float* bnorm);
+                        const void* Ym, const float* bnorm, int pb);
 
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);

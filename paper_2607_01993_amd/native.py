@@ -78,6 +78,9 @@ SIGNATURES = {
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "silh_coh_sep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
+    "silh_set_tuning": (ctypes.c_int, [ctypes.c_int]),
+    "silh_tuning_choice": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_int)]),
     "silh_sample_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SilhSampleInfo)]),
     "silh_philox_uniform": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -417,6 +420,20 @@ def gl_pps_s(X, labels, k, m, t, seed, rows_seed, metric="eucl", prec="fp32", sa
     res["rows"] = rows
     silh_destroy(ctx)
     return res
+
+
+def silh_set_tuning(mode):
+    """0 built-in block shape, 1 autotune (default), 2 / 3 force one / two
+    32-element blocks per wave (matrix-core Phase 2)."""
+    _check(load_library().silh_set_tuning(int(mode)), "silh_set_tuning")
+
+
+def silh_tuning_choice(metric, prec, d, S_pad):
+    pb = ctypes.c_int()
+    _check(load_library().silh_tuning_choice(METRICS[metric] if isinstance(metric, str) else int(metric),
+                                             PRECS[prec] if isinstance(prec, str) else int(prec), int(d),
+                                             int(S_pad), ctypes.byref(pb)), "silh_tuning_choice")
+    return int(pb.value)
 
 
 class _DevArray:
