@@ -15,28 +15,28 @@ namespace silh {
 // beyond the true dimension) to one float64 row y (stride DM, zero-padded),
 // for the metric M.  Zero coordinates add exact zeros, so the padding does
 // not change the value.
-template <int M, int DM>
-__device__ __forceinline__ double dist64(const float (&x)[DM], double nx2, const double* __restrict__ y) {
-  double acc = 0.0, dot = 0.0, ny2 = 0.0;
-#pragma unroll
-  for (int c = 0; c < DM; ++c) {
-    const double xc = (double)x[c];
-    const double yc = y[c];
-    if (M == kEucl) {
-      const double df = xc - yc;
-      acc = acc + df * df;
-    } else if (M == kManh) {
-      acc = acc + fabs(xc - yc);
-    } else if (M == kCanb) {
-      const double num = fabs(xc - yc);
-      const double den = fabs(xc) + fabs(yc);
-      const double term = den > 0.0 ? num / den : 0.0;
-      acc = acc + term;
-    } else {
-      dot = dot + xc * yc;
-      ny2 = ny2 + yc * yc;
-    }
+// One coordinate of a float64 distance, in coordinate order with one rounding
+// per operation (the oracle's order), and the final step.
+template <int M>
+__device__ __forceinline__ void dist64_step(double& acc, double& dot, double& ny2, double xc, double yc) {
+  if (M == kEucl) {
+    const double df = xc - yc;
+    acc = acc + df * df;
+  } else if (M == kManh) {
+    acc = acc + fabs(xc - yc);
+  } else if (M == kCanb) {
+    const double num = fabs(xc - yc);
+    const double den = fabs(xc) + fabs(yc);
+    const double term = den > 0.0 ? num / den : 0.0;
+    acc = acc + term;
+  } else {
+    dot = dot + xc * yc;
+    ny2 = ny2 + yc * yc;
   }
+}
+
+template <int M>
+__device__ __forceinline__ double dist64_final(double acc, double dot, double ny2, double nx2) {
   if (M == kEucl) return __dsqrt_rn(acc);
   if (M == kCos) {
     const double den = __dsqrt_rn(nx2) * __dsqrt_rn(ny2);
@@ -45,6 +45,25 @@ __device__ __forceinline__ double dist64(const float (&x)[DM], double nx2, const
     return v < 0.0 ? 0.0 : (v > 2.0 ? 2.0 : v);
   }
   return acc;
+}
+
+// the element's row in registers
+template <int M, int DM>
+__device__ __forceinline__ double dist64(const float (&x)[DM], double nx2, const double* __restrict__ y) {
+  double acc = 0.0, dot = 0.0, ny2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < DM; ++c) dist64_step<M>(acc, dot, ny2, (double)x[c], y[c]);
+  return dist64_final<M>(acc, dot, ny2, nx2);
+}
+
+// the element's row in LDS, one column per lane (x[c * 64])
+template <int M, int DM>
+__device__ __forceinline__ double dist64_col(const float* __restrict__ x, double nx2,
+                                             const double* __restrict__ y) {
+  double acc = 0.0, dot = 0.0, ny2 = 0.0;
+#pragma unroll 16
+  for (int c = 0; c < DM; ++c) dist64_step<M>(acc, dot, ny2, (double)x[c * kWave], y[c]);
+  return dist64_final<M>(acc, dot, ny2, nx2);
 }
 
 // x row -> registers (vector loads when the row is 16-byte aligned), and its
@@ -73,6 +92,21 @@ __device__ __forceinline__ double load_row(const float* __restrict__ X, int d, i
   if (M == kCos) {
 #pragma unroll
     for (int c = 0; c < DM; ++c) nx2 = nx2 + (double)x[c] * (double)x[c];
+  }
+  return nx2;
+}
+
+// Rows too long for registers (d > 128): one wave per block keeps each lane's
+// row in LDS, column-major (xs[c * 64 + lane], conflict-free), 64 KB.
+constexpr int kWideDM = 256;
+template <int M>
+__device__ __forceinline__ double load_row_col(const float* __restrict__ X, int d, int g, float* __restrict__ xs) {
+  const float* xr = X + (size_t)g * d;
+  double nx2 = 0.0;
+  for (int c = 0; c < kWideDM; ++c) {
+    const float v = c < d ? xr[c] : 0.0f;
+    xs[c * kWave] = v;
+    if (M == kCos) nx2 = nx2 + (double)v * (double)v;
   }
   return nx2;
 }
@@ -168,6 +202,33 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
   }
 }
 
+// d > 128: one wave per item of up to 64 members
+template <int M>
+__global__ __launch_bounds__(kWave) void k_w_partial_wide(const int32_t* __restrict__ items,
+                                                          const int32_t* __restrict__ perm,
+                                                          const float* __restrict__ X, int d,
+                                                          const double* __restrict__ f0X,
+                                                          double* __restrict__ partial) {
+  __shared__ float xs[kWideDM * kWave];
+  __shared__ double sh[1];
+  const int32_t* it = items + (size_t)blockIdx.x * 6;
+  const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
+  const int r = begin + threadIdx.x;
+  const bool have = r < end;
+  float* xl = xs + threadIdx.x;
+  double nx2 = 0.0;
+  if (have) {
+    nx2 = load_row_col<M>(X, d, perm[r], xl);
+  } else {
+    for (int c = 0; c < kWideDM; ++c) xl[c * kWave] = 0.0f;
+  }
+  for (int e = 0; e < f0n; ++e) {
+    const double dv = dist64_col<M, kWideDM>(xl, nx2, f0X + (size_t)(f0b + e) * kWideDM);
+    const double tot = block_sum_f64<kWave>(have ? dv : 0.0, sh);
+    if (threadIdx.x == 0) partial[pb + e] = tot;
+  }
+}
+
 #define SILH_P1_DISPATCH(KERNEL, GRID, ...)                                                   \
   do {                                                                                        \
     switch (metric * 8 + (DM == 8 ? 0 : DM == 16 ? 1 : DM == 32 ? 2 : DM == 64 ? 3 : 4)) {    \
@@ -197,6 +258,17 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
 void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, int nitems,
                       const int32_t* perm, const float* X, int d, const double* f0X, double* partial) {
   if (nitems <= 0) return;
+  if (DM == kWideDM) {
+#define SILH_WP(MM) hipLaunchKernelGGL(k_w_partial_wide<MM>, dim3(nitems), dim3(kWave), 0, st, items, perm, X, d, f0X, partial)
+    switch (metric) {
+      case kEucl: SILH_WP(kEucl); break;
+      case kCos: SILH_WP(kCos); break;
+      case kManh: SILH_WP(kManh); break;
+      default: SILH_WP(kCanb); break;
+    }
+#undef SILH_WP
+    return;
+  }
   SILH_P1_DISPATCH(k_w_partial, dim3(nitems), items, perm, X, d, f0X, partial);
 }
 
@@ -285,10 +357,67 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
   flag[i] = sel;
 }
 
+// d > 128: one wave per block, the element's row in LDS
+template <int M>
+__global__ __launch_bounds__(kWave) void k_draw_wide(int sampler, const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ slab, int n,
+                                                     const float* __restrict__ X, int d,
+                                                     const int32_t* __restrict__ csize, int64_t t,
+                                                     uint64_t seed, const int32_t* __restrict__ f0_off,
+                                                     const double* __restrict__ f0X,
+                                                     const double* __restrict__ W,
+                                                     double* __restrict__ p_gid, int32_t* __restrict__ flag) {
+  __shared__ float xs[kWideDM * kWave];
+  const int i = blockIdx.x * kWave + threadIdx.x;
+  if (i >= n) return;
+  const int g = perm[i];
+  const int j = slab[i];
+  const int64_t m = csize[j];
+  double p;
+  int32_t sel;
+  if (m <= t) {
+    p = 1.0;
+    sel = 1;
+  } else if (sampler == 1) {
+    p = (double)t / (double)m;
+    p = p < 1.0 ? p : 1.0;
+    sel = uniform53(seed, (uint64_t)g, kStreamUNI) < p ? 1 : 0;
+  } else {
+    double gam = 1.0 / (double)m;
+    float* xl = xs + threadIdx.x;
+    const double nx2 = load_row_col<M>(X, d, g, xl);
+    const int fb = f0_off[j], fe = f0_off[j + 1];
+    for (int e = fb; e < fe; ++e) {
+      const double w = W[e];
+      const double dv = dist64_col<M, kWideDM>(xl, nx2, f0X + (size_t)e * kWideDM);
+      if (w > 0.0) {
+        const double r = dv / w;
+        gam = r > gam ? r : gam;
+      }
+    }
+    p = (double)t * gam;
+    p = p < 1.0 ? p : 1.0;
+    sel = uniform53(seed, (uint64_t)g, kStreamPPS) < p ? 1 : 0;
+  }
+  p_gid[g] = p;
+  flag[i] = sel;
+}
+
 void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t* perm,
                  const int32_t* slab, int n, const float* X, int d, const int32_t* csize, int64_t t,
                  uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
                  double* p_gid, int32_t* flag) {
+  if (DM == kWideDM) {
+#define SILH_DW(MM) hipLaunchKernelGGL(k_draw_wide<MM>, dim3((int)ceil_div(n, kWave)), dim3(kWave), 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag)
+    switch (metric) {
+      case kEucl: SILH_DW(kEucl); break;
+      case kCos: SILH_DW(kCos); break;
+      case kManh: SILH_DW(kManh); break;
+      default: SILH_DW(kCanb); break;
+    }
+#undef SILH_DW
+    return;
+  }
   SILH_P1_DISPATCH(k_draw, dim3((int)ceil_div(n, 256)), sampler, perm, slab, n, X, d, csize, t, seed,
                    f0_off, f0X, W, p_gid, flag);
 }

@@ -673,6 +673,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
 // below is the measured choice on the benchmark workload; the autotuner may
 // pick per (metric, operands, d, sample size).  fp8 always uses one.
 int mfma_pb_default(int prec, int DM) { return (prec == 0 && DM <= 32) ? 2 : 1; }
+int mfma_pb_max(int prec, int DM) { return (prec == 2 || DM > 128) ? 1 : 2; }
 
 template <int M, int P, int DM, int PB>
 static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
@@ -686,7 +687,7 @@ static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, con
 template <int M, int P, int DM>
 static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
                             const float* bnorm, int pb) {
-  if constexpr (P != 2) {
+  if constexpr (P != 2 && DM <= 128) {  // two blocks per wave would not fit the registers beyond
     if (pb == 2) {
       launch_mfma_pb<M, P, DM, 2>(st, A, mu, Ym, bnorm);
       return;
@@ -720,6 +721,7 @@ static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, 
         case 32: FN<kEucl, 1, 32>(__VA_ARGS__); return true;            \
         case 64: FN<kEucl, 1, 64>(__VA_ARGS__); return true;            \
         case 128: FN<kEucl, 1, 128>(__VA_ARGS__); return true;          \
+        case 256: FN<kEucl, 1, 256>(__VA_ARGS__); return true;          \
       }                                                                 \
     } else if (metric == kCos && prec == 0) {                           \
       switch (DM) {                                                     \
@@ -736,6 +738,7 @@ static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, 
         case 32: FN<kCos, 1, 32>(__VA_ARGS__); return true;             \
         case 64: FN<kCos, 1, 64>(__VA_ARGS__); return true;             \
         case 128: FN<kCos, 1, 128>(__VA_ARGS__); return true;           \
+        case 256: FN<kCos, 1, 256>(__VA_ARGS__); return true;           \
       }                                                                 \
     } else if (metric == kCos && prec == 2) {                           \
       switch (DM) {                                                     \
@@ -744,6 +747,7 @@ static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, 
         case 32: FN<kCos, 2, 32>(__VA_ARGS__); return true;             \
         case 64: FN<kCos, 2, 64>(__VA_ARGS__); return true;             \
         case 128: FN<kCos, 2, 128>(__VA_ARGS__); return true;           \
+        case 256: FN<kCos, 2, 256>(__VA_ARGS__); return true;           \
       }                                                                 \
     }                                                                   \
     return false;                                                       \

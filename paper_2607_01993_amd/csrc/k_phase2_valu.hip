@@ -18,43 +18,47 @@ namespace silh {
 
 constexpr int kGroup = 32;  // samples summed in float32 before the float64 add
 
+// One coordinate of a float32 distance, and the final step.  Cosine runs as
+// half the squared distance of the unit vectors plus u (0.5 for a zero vector,
+// else 0): for unit x_hat, y_hat, 1 - x_hat.y_hat = |x_hat - y_hat|^2 / 2, and
+// the u terms give 1 whenever either vector is zero; this form does not
+// cancel for near-parallel pairs.
+template <int M>
+__device__ __forceinline__ float dist32_step(float s, float xc, float yc) {
+  if (M == kManh) return s + fabsf(xc - yc);
+  if (M == kCanb) {
+    const float den = fmaxf(fabsf(xc) + fabsf(yc), FLT_MIN);
+    return fmaf(fabsf(xc - yc), __builtin_amdgcn_rcpf(den), s);
+  }
+  const float df = xc - yc;  // Euclidean, cosine
+  return fmaf(df, df, s);
+}
+
+template <int M>
+__device__ __forceinline__ float dist32_final(float s, float ux, float uy) {
+  if (M == kEucl) return __builtin_amdgcn_sqrtf(s);
+  if (M == kCos) return __builtin_amdgcn_fmed3f(fmaf(0.5f, s, ux + uy), 0.0f, 2.0f);
+  return s;
+}
+
+// the element's row in registers
 template <int M, int DM>
 __device__ __forceinline__ float dist32(const float (&x)[DM], const float* __restrict__ y, float ux,
                                       float uy) {
-  if (M == kEucl) {
-    float s = 0.f;
+  float s = 0.f;
 #pragma unroll
-    for (int c = 0; c < DM; ++c) {
-      const float df = x[c] - y[c];
-      s = fmaf(df, df, s);
-    }
-    return __builtin_amdgcn_sqrtf(s);
-  } else if (M == kManh) {
-    float s = 0.f;
-#pragma unroll
-    for (int c = 0; c < DM; ++c) s += fabsf(x[c] - y[c]);
-    return s;
-  } else if (M == kCanb) {
-    float s = 0.f;
-#pragma unroll
-    for (int c = 0; c < DM; ++c) {
-      const float den = fmaxf(fabsf(x[c]) + fabsf(y[c]), FLT_MIN);
-      s = fmaf(fabsf(x[c] - y[c]), __builtin_amdgcn_rcpf(den), s);
-    }
-    return s;
-  } else {
-    // cosine, as half the squared distance of the unit vectors plus u (0.5
-    // for a zero vector, else 0): for unit x_hat, y_hat,
-    // 1 - x_hat.y_hat = |x_hat - y_hat|^2 / 2, and the u terms give 1 whenever
-    // either vector is zero; this form does not cancel for near-parallel pairs.
-    float s = 0.f;
-#pragma unroll
-    for (int c = 0; c < DM; ++c) {
-      const float df = x[c] - y[c];
-      s = fmaf(df, df, s);
-    }
-    return __builtin_amdgcn_fmed3f(fmaf(0.5f, s, ux + uy), 0.0f, 2.0f);
-  }
+  for (int c = 0; c < DM; ++c) s = dist32_step<M>(s, x[c], y[c]);
+  return dist32_final<M>(s, ux, uy);
+}
+
+// the element's row in LDS, one column per lane (x[c * 64])
+template <int M, int DM>
+__device__ __forceinline__ float dist32_col(const float* __restrict__ x, const float* __restrict__ y, float ux,
+                                          float uy) {
+  float s = 0.f;
+#pragma unroll 32
+  for (int c = 0; c < DM; ++c) s = dist32_step<M>(s, x[c * kWave], y[c]);
+  return dist32_final<M>(s, ux, uy);
 }
 
 template <int M, int DM>
@@ -125,14 +129,86 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
   if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
 }
 
+// d > 128: one wave per block, each lane's row in LDS (column-major, 64 KB);
+// otherwise as k_p2_valu
+constexpr int kWideDM = 256;
+template <int M>
+__global__ __launch_bounds__(kWave) void k_p2_valu_wide(
+    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+    const float* __restrict__ Y, const float* __restrict__ w, const float* __restrict__ aux,
+    const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
+    float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
+    float* __restrict__ What, double* __restrict__ bpart) {
+  __shared__ float xs[kWideDM * kWave];
+  __shared__ double sh[1];
+  const int e = blockIdx.x * kWave + threadIdx.x;
+  const bool valid = e < n;
+  const int er = valid ? e : n - 1;
+  float* xl = xs + threadIdx.x;
+  const float* xr = X + (size_t)er * d;
+  float s2 = 0.f;
+  for (int c = 0; c < kWideDM; ++c) {
+    const float v = c < d ? xr[c] : 0.0f;
+    xl[c * kWave] = v;
+    s2 = fmaf(v, v, s2);
+  }
+  float ux = 0.f;
+  if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
+    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+    ux = s2 > 0.f ? 0.f : 0.5f;
+    for (int c = 0; c < kWideDM; ++c) xl[c * kWave] *= rx;
+  }
+  const int own = labels[er];
+  double w_own = 0.0;
+  double bmin = __builtin_inf();
+  for (int j = 0; j < k; ++j) {
+    const int s0 = sp_off[j];
+    const int cj = cnt[j];
+    double accd = 0.0;
+    for (int g0 = 0; g0 < cj; g0 += kGroup) {
+      const int g1 = g0 + kGroup < cj ? g0 + kGroup : cj;
+      float acc = 0.f;
+      for (int q = g0; q < g1; ++q) {
+        const float* y = Y + (size_t)(s0 + q) * kWideDM;
+        const float uy = M == kCos ? aux[s0 + q] : 0.f;
+        acc = fmaf(w[s0 + q], dist32_col<M, kWideDM>(xl, y, ux, uy), acc);
+      }
+      accd += (double)acc;
+    }
+    if (What != nullptr && valid) What[(size_t)e * k + j] = (float)accd;
+    const int sz = csize[j];
+    if (j == own) {
+      w_own = accd;
+    } else if (sz > 0) {
+      const double bj = accd / (double)sz;
+      bmin = bj < bmin ? bj : bmin;
+    }
+  }
+  const int szo = csize[own];
+  const double a = szo > 1 ? w_own / (double)(szo - 1) : 0.0;
+  const double b = bmin;
+  const double mx = a > b ? a : b;
+  const double sv = (szo > 1 && mx > 0.0) ? (b - a) / mx : 0.0;
+  if (valid) {
+    if (a_out) a_out[e] = (float)a;
+    if (b_out) b_out[e] = (float)b;
+    if (s_out) s_out[e] = (float)sv;
+  }
+  const double tot = block_sum_f64<kWave>(valid ? sv : 0.0, sh);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
+}
+
 int phase2_valu_dm(int d) {
   if (d <= 8) return 8;
   if (d <= 16) return 16;
   if (d <= 32) return 32;
   if (d <= 64) return 64;
   if (d <= 128) return 128;
+  if (d <= kWideDM) return kWideDM;
   return 0;
 }
+
+int phase2_valu_rows(int DM) { return DM == kWideDM ? kWave : kP2Rows; }
 
 template <int M, int DM>
 static void launch_one(hipStream_t st, const P2Args& A) {
@@ -149,6 +225,11 @@ static bool launch_metric(hipStream_t st, int DM, const P2Args& A) {
     case 32: launch_one<M, 32>(st, A); return true;
     case 64: launch_one<M, 64>(st, A); return true;
     case 128: launch_one<M, 128>(st, A); return true;
+    case kWideDM:
+      hipLaunchKernelGGL(k_p2_valu_wide<M>, dim3((int)ceil_div(A.n, kWave)), dim3(kWave), 0, st, A.X, A.n, A.d,
+                         A.labels, A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What,
+                         A.bpart);
+      return true;
     default: return false;
   }
 }

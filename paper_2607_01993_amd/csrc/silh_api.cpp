@@ -298,7 +298,7 @@ silh_status check_params(const silh_params* prm, const float* X, const int32_t* 
   if (prm->prec == SILH_FP8 && prm->d < kFp8MinD)
     return fail(SILH_E_UNSUPPORTED, "fp8 operands need d >= %d (d=%d)", kFp8MinD, prm->d);
   if (phase2_valu_dm(prm->d) == 0)
-    return fail(SILH_E_UNSUPPORTED, "d=%d has no Phase-2 kernel (d <= 128)", prm->d);
+    return fail(SILH_E_UNSUPPORTED, "d=%d has no Phase-2 kernel", prm->d);
   int64_t t = prm->t;
   if (!exact) {
     if (prm->sampler < 0 || prm->sampler > 1) return fail(SILH_E_ARG, "unknown sampler %d", prm->sampler);
@@ -393,10 +393,12 @@ silh_status create(const silh_params* prm, const float* X, const int32_t* labels
   c->d = prm->d;
   c->k = prm->k;
   c->DM = phase2_valu_dm(prm->d);
+  // float32 operands of d > 128 do not fit the MFMA kernel's registers: the
+  // vector-ALU kernel takes them
   c->mfma = (prm->metric == SILH_EUCL || prm->metric == SILH_COS) &&
-            (prm->prec == SILH_FP32 || prm->prec == SILH_BF16 || prm->prec == SILH_FP8);
+            (prm->prec == SILH_BF16 || prm->prec == SILH_FP8 || (prm->prec == SILH_FP32 && c->DM <= 128));
   c->mprec = prm->prec == SILH_BF16 ? 1 : (prm->prec == SILH_FP8 ? 2 : 0);
-  c->p2_rows = c->mfma ? phase2_mfma_rows(c->mprec, c->DM) : kP2Rows;
+  c->p2_rows = c->mfma ? phase2_mfma_rows(c->mprec, c->DM) : phase2_valu_rows(c->DM);
   silh_status s = build_index(c);
   if (s != SILH_OK) {
     std::string msg = g_err;
@@ -527,13 +529,15 @@ silh_status phase1(silh_ctx* c) {
   c->citem_first_h.assign(k, 0);
   c->citem_count_h.assign(k, 0);
   int64_t pbase = 0;
+  // members per work item: one per thread of the W-pass block
+  const int chunk = c->DM > 128 ? kWChunkWide : kWChunk;
   if (pps && c->F0 > 0) {
     for (int j = 0; j < k; ++j) {
       const int fj = c->f0_off32_h[j + 1] - c->f0_off32_h[j];
       c->citem_first_h[j] = (int32_t)(c->items_h.size() / 6);
       if ((int64_t)c->csize_h[j] <= c->t || fj == 0) continue;
-      for (int b = c->off_h[j]; b < c->off_h[j + 1]; b += kWChunk) {
-        const int e = b + kWChunk < c->off_h[j + 1] ? b + kWChunk : c->off_h[j + 1];
+      for (int b = c->off_h[j]; b < c->off_h[j + 1]; b += chunk) {
+        const int e = b + chunk < c->off_h[j + 1] ? b + chunk : c->off_h[j + 1];
         c->items_h.insert(c->items_h.end(), {j, b, e, c->f0_off32_h[j], fj, (int32_t)pbase});
         pbase += fj;
         c->citem_count_h[j] += 1;
@@ -598,7 +602,7 @@ int size_bucket(int64_t S_pad) {
 }
 
 int pick_pb(silh_ctx* c, const P2Args& A) {
-  if (c->mprec == 2) return 1;
+  if (mfma_pb_max(c->mprec, c->DM) == 1) return 1;
   const int mode = g_tune_mode.load();
   if (mode == 0) return mfma_pb_default(c->mprec, c->DM);
   if (mode == 2 || mode == 3) return mode - 1;

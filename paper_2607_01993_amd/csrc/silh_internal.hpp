@@ -12,6 +12,7 @@ constexpr int kSortSeg = 1024;
 constexpr int kScanTile = 2048;
 // Members per work item of the W(e_bar) partial sums.
 constexpr int kWChunk = 256;   // one member per thread of a 256-thread block
+constexpr int kWChunkWide = 64;  // d > 128: one member per lane of a one-wave block
 // Sample rows of each cluster are padded to a multiple of this.
 constexpr int kSamplePad = 32;
 // Rows per Phase-2 block in the VALU kernel.
@@ -79,6 +80,7 @@ struct P2Args {
 // returns false if (metric, d) has no VALU kernel
 bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& a);
 int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if unsupported
+int phase2_valu_rows(int DM);  // elements per block (and per partial of the mean) of the VALU kernel
 
 // MFMA path (Euclidean and cosine with float32 or bf16 operands; cosine with
 // fp8 operands).  prec: 0 float32, 1 bf16, 2 fp8.
@@ -95,6 +97,7 @@ int phase2_mfma_rows(int prec, int DM);
 // 32-element blocks per wave: the default choice, and the launcher (pb 1 or
 // 2; fp8 always runs with 1)
 int mfma_pb_default(int prec, int DM);
+int mfma_pb_max(int prec, int DM);
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
                         const void* Ym, const float* bnorm, int pb);
 

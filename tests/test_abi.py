@@ -66,7 +66,7 @@ def _init(**kw):
     (dict(delta=1.0), 1), (dict(t=0, eps=0.0), 1), (dict(t=0, eps=1.5), 1),
     (dict(reserved0=1), 1), (dict(prec=1, metric=2), 7), (dict(prec=2, metric=3), 7), (dict(prec=1, metric=3), 7),
     (dict(prec=2, metric=0), 7), (dict(prec=2, metric=1, d=63), 7), (dict(prec=4), 1),
-    (dict(d=200), 7),
+    (dict(d=300), 1),
 ])
 def test_init_rejects_bad_params(kw, status):
     st, msg, out = _init(**kw)

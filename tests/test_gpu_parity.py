@@ -141,6 +141,44 @@ def test_mfma_dims(metric, prec, d):
     native.silh_destroy(ctx)
 
 
+@pytest.mark.parametrize("metric,prec", COMBOS)
+@pytest.mark.parametrize("d", [200, 256])
+def test_wide_rows(metric, prec, d):
+    """d > 128: Phase 1 and the vector-ALU Phase 2 keep rows in LDS, bf16
+    stays on the matrix cores; sample sets bit-exact, scores to the bars,
+    with a singleton cluster and n not a multiple of any block."""
+    X, L = synth.tiny_case(2300 + d, d, 5, seed=d + 1)
+    L = L.copy()
+    L[L == 4] = 3
+    L[9] = 4
+    Xd, Ld = dev(X, L)
+    ctx = native.silh_sample_init(Xd, Ld, 5, metric, prec, t=40, seed=d)
+    native.silh_pps_sample(ctx)
+    smp = oracle.sample(X, L, 5, metric, 40, 0.01, d)
+    view = native.silh_sample_view(ctx)
+    assert_same_sets(smp, view, X.shape[0], d, "pps", 40)
+    np.testing.assert_allclose(view["f0_W"], np.concatenate([smp["W0"][j] for j in range(5)]),
+                               rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(view["p"], smp["p"], rtol=1e-12)
+    est = oracle.estimate(X, L, 5, metric, smp)
+    gpu = native.silh_scores(ctx)
+    compare_scores(gpu, est, prec=prec)
+    assert abs(gpu["mean"] - est["mean"]) <= mean_tol(prec)
+    native.silh_destroy(ctx)
+
+
+def test_wide_rows_fp8_and_exact():
+    X, L = synth.vmf_blobs(3000, 256, 4, seed=7, kappa=60.0)
+    Xd, Ld = dev(X, L)
+    gpu = native.silh_exact(Xd, Ld, 4, "cos", "fp8")
+    ref = oracle.exact(X, L, 4, "cos")
+    assert abs(gpu["mean"] - ref["mean"]) <= LOWP_MEAN_ATOL
+    compare_scores(gpu, ref, prec="fp8")
+    gpu = native.silh_exact(Xd, Ld, 4, "eucl", "bf16")
+    ref = oracle.exact(X, L, 4, "eucl")
+    compare_scores(gpu, ref, prec="bf16")
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("d", [16, 64, 128])
 def test_cosine_directional(prec, d):
