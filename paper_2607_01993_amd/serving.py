@@ -5,7 +5,7 @@ datasets, with Poisson arrivals, through the library's serving runtime
     python -m paper_2607_01993_amd.serving [--requests R] [--workers W] [--out FILE]
 
 Workload: 32 resident datasets (n log-uniform in [1e4, 2e6], d in {16, 64,
-128}, one metric each: Euclidean and cosine in bf16 MFMA, Manhattan and
+256}, one metric each: Euclidean and cosine in bf16 MFMA, Manhattan and
 Canberra in float32), requests with k ~ U{2..128} (Voronoi clusterings), t
 in {64, 256, 1024}, delta = 0.01.  First a closed run (every request queued at
 once) gives the saturation rate; then for each load factor f the same request
@@ -136,7 +136,7 @@ def main():
         log(f"load {f}: {s}")
     srv.close()
     out = {
-        "workload": "serving pool: 32 datasets n~10^U[4,log10 2e6], d in {16,64,128}, metric per dataset "
+        "workload": "serving pool: 32 datasets n~10^U[4,log10 2e6], d in {16,64,256}, metric per dataset "
                     "(eucl/cos bf16 MFMA, manh/canb fp32), k~U{2..128} Voronoi, t in {64,256,1024}, delta 0.01",
         "requests": len(reqs), "workers": args.workers, "saturation_req_s": sat,
         "closed_run": closed, "weighted_dist_evals_per_s_closed": pairs / secs, "loads": loads,

@@ -206,7 +206,7 @@ def config_sweep(n: int = 500_000, d: int = 64, blobs: int = 16, seed: int = 3):
 SERVING_METRICS = ("eucl", "cos", "manh", "canb")
 
 
-def serving_pool_specs(count: int = 32, seed: int = 5, dims=(16, 64, 128), n_range=(1e4, 2e6)):
+def serving_pool_specs(count: int = 32, seed: int = 5, dims=(16, 64, 256), n_range=(1e4, 2e6)):
     """The resident datasets of the serving workload: n = round(10^U[log10
     n_range]), d from dims, a metric each (its data family follows it)."""
     rng = np.random.default_rng(seed)
