@@ -346,6 +346,21 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   static_assert(C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
   constexpr float S2 = kFp8Scale * kFp8Scale;
   __shared__ double sh32[4 * PB];  // 32-element partials of the block, in element order
+  // long rows (HALF > 40): LDS tiles of 32 packed rows, rows padded by 16
+  // bytes so that the lanes' 16-byte reads fall in different banks
+  constexpr int kRowB = C::KP * C::ELEM;
+  constexpr int kLRow = kRowB + 16;
+  constexpr int kTileB = 32 * kLRow;
+  constexpr int kChRow = kRowB / 16;
+  constexpr int kNCh = 32 * kChRow;
+  constexpr int kPer = (kNCh + 255) / 256;
+  constexpr bool kLds = C::HALF > 40;
+  __shared__ __attribute__((aligned(16))) unsigned char ldsB[kLds ? 2 * kTileB : 16];
+  __shared__ float ldsW[2][32];
+  __shared__ int ldsG[2][32];
+  u32x4 stage[kLds ? kPer : 1];
+  float sw = 0.f;
+  int sg = -1;
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int col = lane & 31;
@@ -538,23 +553,27 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
     }
     int g = 0;
-    auto tile = [&](const BFrag<P, DM>& bf, float wj, int gj, bool last) {
+    // one tile: getB(q) gives step q of this lane's B fragment (a float2 of
+    // two steps for float32), from registers or read from LDS just in time
+    auto tile = [&](auto&& getB, float wj, int gj, bool last) {
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
         f32x16 c;
         if constexpr (P == 0) {
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[0], bf.v[0].x, f32x16{}, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[1], bf.v[0].y, c, 0, 0, 0);
+          const float2 b0 = getB(0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[0], b0.x, f32x16{}, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[1], b0.y, c, 0, 0, 0);
 #pragma unroll
           for (int s2 = 1; s2 < C::NSTEP / 2; ++s2) {
-            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2], bf.v[s2].x, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2 + 1], bf.v[s2].y, c, 0, 0, 0);
+            const float2 bq = getB(s2);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2], bq.x, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2 + 1], bq.y, c, 0, 0, 0);
           }
         } else if constexpr (P == 1) {
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[0], bf.v[0], f32x16{}, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[0], getB(0), f32x16{}, 0, 0, 0);
 #pragma unroll
           for (int s = 1; s < C::NSTEP; ++s)
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[s], bf.v[s], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[s], getB(s), c, 0, 0, 0);
         } else {
           // fp8: the accumulator starts at 64^2 (row term + column term), the
           // MFMA adds -64^2 x~_q . y~_q (unscaled f8f6f4 form, e4m3 operands)
@@ -563,7 +582,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
           for (int r = 0; r < 16; ++r) c[r] = nxc[b][r] + bcol;
 #pragma unroll
           for (int s = 0; s < C::NSTEP; ++s)
-            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], bf.v[s], c, 0, 0, 0, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], getB(s), c, 0, 0, 0, 0, 0, 0);
         }
         if (M == kEucl) {
           // d(e, e) = 0 exactly: the expanded form leaves rounding noise
@@ -600,13 +619,58 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       }
     };
     if constexpr (C::HALF > 40) {
-      // long rows: one B buffer (registers go to occupancy instead)
-      BFrag<P, DM> b0;
-      float w0 = 0.f;
-      int g0 = -1;
+      // Long rows: the block's four waves sweep the same tiles, so each tile
+      // is loaded once per block into LDS (double-buffered: tile t + 1 is
+      // fetched into registers while tile t is computed, then stored to the
+      // other buffer), and every wave reads its B fragment from there.
+      auto fetch = [&](int row0) {
+        const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)row0 * (size_t)kRowB, 32 * kRowB);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+          const int ci = threadIdx.x + 256 * i;
+          stage[i] = ci < kNCh ? __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)ci, 0, 0) : u32x4{};
+        }
+        if (threadIdx.x < 32) {
+          sw = w[row0 + threadIdx.x];
+          sg = P == 2 ? __float_as_int(bnorm[row0 + threadIdx.x]) : gid_pk[row0 + threadIdx.x];
+        }
+      };
+      auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+          const int ci = threadIdx.x + 256 * i;
+          if (ci < kNCh) {
+            const int r = ci / kChRow, q = ci - r * kChRow;
+            *(u32x4*)(ldsB + buf * kTileB + r * kLRow + 16 * q) = stage[i];
+          }
+        }
+        if (threadIdx.x < 32) {
+          ldsW[buf][threadIdx.x] = sw;
+          ldsG[buf][threadIdx.x] = sg;
+        }
+      };
+      if (ntile > 0) {
+        fetch(base);
+        store(0);
+      }
+      __syncthreads();
       for (int t = 0; t < ntile; ++t) {
-        load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + t * 32, lane_off, col, b0, w0, g0);
-        tile(b0, w0, g0, t + 1 == ntile);
+        const int buf = t & 1;
+        if (t + 1 < ntile) fetch(base + (t + 1) * 32);
+        const unsigned char* tl = ldsB + buf * kTileB + col * kLRow + h * C::HALF * C::ELEM;
+        auto fromLds = [&](int q) {
+          if constexpr (P == 0) {
+            return *(const float2*)(tl + 8 * q);
+          } else if constexpr (P == 1) {
+            return *(const bf16x8*)(tl + 16 * q);
+          } else {
+            const u32x4 lo = *(const u32x4*)(tl + 32 * q), hi = *(const u32x4*)(tl + 32 * q + 16);
+            return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+          }
+        };
+        tile(fromLds, ldsW[buf][col], ldsG[buf][col], t + 1 == ntile);
+        if (t + 1 < ntile) store(buf ^ 1);
+        __syncthreads();
       }
     } else {
       // Tiles go in pairs with unconditional prefetches (the one past the
@@ -620,12 +684,12 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       int t = 0;
       for (; t + 2 <= ntile; t += 2) {
         load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
-        tile(b0, w0, g0, false);
+        tile([&](int q) { return b0.v[q]; }, w0, g0, false);
         const int t2 = t + 2 < ntile ? t + 2 : ntile - 1;
         load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + t2 * 32, lane_off, col, b0, w0, g0);
-        tile(b1, w1, g1, t + 2 == ntile);
+        tile([&](int q) { return b1.v[q]; }, w1, g1, t + 2 == ntile);
       }
-      if (t < ntile) tile(b0, w0, g0, true);
+      if (t < ntile) tile([&](int q) { return b0.v[q]; }, w0, g0, true);
     }
     const int sz = csize[j];
 #pragma unroll

@@ -61,23 +61,31 @@ __device__ __forceinline__ float dist32_col(const float* __restrict__ x, const f
   return dist32_final<M>(s, ux, uy);
 }
 
-template <int M, int DM>
+// PASS 0: the whole row.  Manhattan and Canberra are sums over coordinates,
+// so for d > 128 each cluster's weighted sum splits exactly into the sums over
+// coordinates [0, 128) and [128, 256): PASS 1 takes the first half and
+// stores the per-cluster float64 sums in Wpart [n][k]; PASS 2 takes the second
+// half (c0 = 128), adds Wpart and finishes.  ystride is the packed sample's
+// row length.
+template <int M, int DM, int PASS>
 __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
     const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const float* __restrict__ Y, const float* __restrict__ w, const float* __restrict__ aux,
     const int32_t* __restrict__ sp_off,
     const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
-    float* __restrict__ What, double* __restrict__ bpart) {
+    float* __restrict__ What, double* __restrict__ bpart, int c0, int ystride,
+    double* __restrict__ Wpart) {
+  static_assert(PASS == 0 || M == kManh || M == kCanb, "only sums over coordinates split");
   __shared__ double sh[kP2Rows / kWave];
   const int e = blockIdx.x * kP2Rows + threadIdx.x;
   const bool valid = e < n;
   const int er = valid ? e : n - 1;
 
   float x[DM];
-  const float* xr = X + (size_t)er * d;
+  const float* xr = X + (size_t)er * d + c0;
 #pragma unroll
-  for (int c = 0; c < DM; ++c) x[c] = c < d ? xr[c] : 0.0f;
+  for (int c = 0; c < DM; ++c) x[c] = c0 + c < d ? xr[c] : 0.0f;
   float ux = 0.f;
   if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
     float s2 = 0.f;
@@ -100,12 +108,17 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
       const int g1 = g0 + kGroup < cj ? g0 + kGroup : cj;
       float acc = 0.f;
       for (int q = g0; q < g1; ++q) {
-        const float* y = Y + (size_t)(s0 + q) * DM;
+        const float* y = Y + (size_t)(s0 + q) * ystride + c0;
         const float uy = M == kCos ? aux[s0 + q] : 0.f;
         acc = fmaf(w[s0 + q], dist32<M, DM>(x, y, ux, uy), acc);
       }
       accd += (double)acc;
     }
+    if (PASS == 1) {
+      if (valid) Wpart[(size_t)e * k + j] = accd;
+      continue;
+    }
+    if (PASS == 2) accd += Wpart[(size_t)er * k + j];
     if (What != nullptr && valid) What[(size_t)e * k + j] = (float)accd;
     const int sz = csize[j];
     if (j == own) {
@@ -115,6 +128,7 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
       bmin = bj < bmin ? bj : bmin;
     }
   }
+  if (PASS == 1) return;
   const int szo = csize[own];
   const double a = szo > 1 ? w_own / (double)(szo - 1) : 0.0;
   const double b = bmin;
@@ -208,13 +222,17 @@ int phase2_valu_dm(int d) {
   return 0;
 }
 
-int phase2_valu_rows(int DM) { return DM == kWideDM ? kWave : kP2Rows; }
+int phase2_valu_rows(int metric, int DM) {
+  return (DM == kWideDM && metric != kManh && metric != kCanb) ? kWave : kP2Rows;
+}
+bool phase2_valu_split(int metric, int DM) { return DM == kWideDM && (metric == kManh || metric == kCanb); }
 
-template <int M, int DM>
-static void launch_one(hipStream_t st, const P2Args& A) {
+template <int M, int DM, int PASS = 0>
+static void launch_one(hipStream_t st, const P2Args& A, int c0 = 0, int ystride = DM) {
   const int blocks = (int)ceil_div(A.n, kP2Rows);
-  hipLaunchKernelGGL((k_p2_valu<M, DM>), dim3(blocks), dim3(kP2Rows), 0, st, A.X, A.n, A.d, A.labels,
-                     A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What, A.bpart);
+  hipLaunchKernelGGL((k_p2_valu<M, DM, PASS>), dim3(blocks), dim3(kP2Rows), 0, st, A.X, A.n, A.d, A.labels,
+                     A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What, A.bpart, c0,
+                     ystride, A.Wpart);
 }
 
 template <int M>
@@ -226,6 +244,13 @@ static bool launch_metric(hipStream_t st, int DM, const P2Args& A) {
     case 64: launch_one<M, 64>(st, A); return true;
     case 128: launch_one<M, 128>(st, A); return true;
     case kWideDM:
+      if constexpr (M == kManh || M == kCanb) {
+        if (A.Wpart != nullptr) {  // two halves through the register kernel
+          launch_one<M, 128, 1>(st, A, 0, kWideDM);
+          launch_one<M, 128, 2>(st, A, 128, kWideDM);
+          return true;
+        }
+      }
       hipLaunchKernelGGL(k_p2_valu_wide<M>, dim3((int)ceil_div(A.n, kWave)), dim3(kWave), 0, st, A.X, A.n, A.d,
                          A.labels, A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What,
                          A.bpart);

@@ -87,7 +87,7 @@ struct silh_ctx {
   int p2_rows = kP2Rows;
   int state = 0;  // 0 = indexed, 1 = sampled
 
-  std::vector<void*> alloc_init, alloc_sample, alloc_rows;
+  std::vector<void*> alloc_init, alloc_sample, alloc_rows, alloc_p2;
 
   // host copies
   std::vector<uint32_t> counts_h;
@@ -398,7 +398,7 @@ silh_status create(const silh_params* prm, const float* X, const int32_t* labels
   c->mfma = (prm->metric == SILH_EUCL || prm->metric == SILH_COS) &&
             (prm->prec == SILH_BF16 || prm->prec == SILH_FP8 || (prm->prec == SILH_FP32 && c->DM <= 128));
   c->mprec = prm->prec == SILH_BF16 ? 1 : (prm->prec == SILH_FP8 ? 2 : 0);
-  c->p2_rows = c->mfma ? phase2_mfma_rows(c->mprec, c->DM) : phase2_valu_rows(c->DM);
+  c->p2_rows = c->mfma ? phase2_mfma_rows(c->mprec, c->DM) : phase2_valu_rows(prm->metric, c->DM);
   silh_status s = build_index(c);
   if (s != SILH_OK) {
     std::string msg = g_err;
@@ -660,6 +660,12 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
   A.s = s;
   A.What = What;
   A.bpart = c->bpart;
+  free_list(c, c->alloc_p2);
+  if (!c->mfma && phase2_valu_split(c->prm.metric, c->DM)) {
+    Carve cv;
+    cv.add(&A.Wpart, (size_t)c->n * c->k);
+    CHK(cv.commit(c, c->alloc_p2));
+  }
   {
     const int pb = c->mfma ? pick_pb(c, A) : 0;  // (tuning runs stay outside the timed launch)
     Launch L(c, K_PHASE2);
@@ -739,6 +745,11 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   A.s = su;
   A.What = nullptr;
   A.bpart = bpu;
+  if (!c->mfma && phase2_valu_split(c->prm.metric, c->DM)) {
+    Carve cv;
+    cv.add(&A.Wpart, (size_t)(mu > 0 ? mu : 1) * c->k);
+    CHK(cv.commit(c, c->alloc_rows));
+  }
   {
     const int pb = c->mfma ? pick_pb(c, A) : 0;  // (tuning runs stay outside the timed launch)
     Launch L(c, K_PHASE2);
@@ -985,6 +996,7 @@ void silh_destroy(silh_ctx* c) {
   }
   c->pending.clear();
   return_events(c->pool);
+  free_list(c, c->alloc_p2);
   free_list(c, c->alloc_rows);
   free_list(c, c->alloc_sample);
   free_list(c, c->alloc_init);

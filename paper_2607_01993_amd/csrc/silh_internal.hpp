@@ -75,12 +75,17 @@ struct P2Args {
   float* b;
   float* s;
   float* What;          // [n][k] or null
-  double* bpart;        // [ceil(n / kP2Rows)]
+  double* bpart;        // [ceil(n / rows per partial)]
+  double* Wpart = nullptr;  // [n][k] float64, for the split vector-ALU pass (d > 128)
 };
 // returns false if (metric, d) has no VALU kernel
 bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& a);
 int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if unsupported
-int phase2_valu_rows(int DM);  // elements per block (and per partial of the mean) of the VALU kernel
+// elements per block (and per partial of the mean) of the VALU kernel
+int phase2_valu_rows(int metric, int DM);
+// d > 128 Manhattan / Canberra run as two coordinate halves and need
+// P2Args::Wpart ([n][k] float64 scratch)
+bool phase2_valu_split(int metric, int DM);
 
 // MFMA path (Euclidean and cosine with float32 or bf16 operands; cosine with
 // fp8 operands).  prec: 0 float32, 1 bf16, 2 fp8.

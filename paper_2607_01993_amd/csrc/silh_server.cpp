@@ -124,7 +124,9 @@ uint64_t estimate_bytes(const Dataset& ds, const silh_request& r) {
   const uint64_t kp = mfma ? (uint64_t)silh::mfma_kp(mprec, DM) : 0;
   const uint64_t row = (uint64_t)DM * 4 + kp * 4 + 24;
   const uint64_t m = r.m > 0 ? (uint64_t)r.m : 0;  // row draws: ids, gathered rows, outputs
-  return 24 * n + S * row + m * ((uint64_t)ds.d * 4 + 32) + ((uint64_t)1 << 20);
+  // d > 128 Manhattan / Canberra: float64 partial sums per element and cluster
+  const uint64_t split = (DM > 128 && (r.metric == SILH_MANH || r.metric == SILH_CANB)) ? n * (uint64_t)r.k * 8 : 0;
+  return 24 * n + S * row + m * ((uint64_t)ds.d * 4 + 32) + split + ((uint64_t)1 << 20);
 }
 
 void run_job(Dataset ds, const silh_request& r, Pool& pool, hipStream_t st, silh_result& res) {
