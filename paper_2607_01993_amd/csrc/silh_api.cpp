@@ -11,6 +11,7 @@
 #include <cstring>
 #include <array>
 #include <atomic>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -118,6 +119,11 @@ struct silh_ctx {
   float *w32 = nullptr, *aux32 = nullptr, *Y32 = nullptr, *mu = nullptr, *bnorm = nullptr;
   void* Ym = nullptr;
   double *bpart = nullptr, *mean_d = nullptr;
+
+  // pinned staging for the small host <-> device transfers (from a
+  // process-wide pool): host-to-device copies from it are asynchronous
+  unsigned char* pin = nullptr;
+  size_t pin_size = 0, pin_used = 0;
 
   // profiling
   bool prof_on = false;
@@ -273,10 +279,102 @@ silh_status drain_prof(silh_ctx* c) {
   return SILH_OK;
 }
 
+// ---- pinned staging ------------------------------------------------------------
+// Blocks of page-locked host memory are shared by the process: a context takes
+// one at its first transfer and returns it at silh_destroy.  Inside a block,
+// transfers take consecutive slices; the slices are reused only after the
+// context's stream has been synchronised (every copy from them is then done).
+std::mutex g_pin_mu;
+std::vector<std::pair<unsigned char*, size_t>> g_pin_free;
+constexpr size_t kPinBlock = (size_t)1 << 18;
+
+void pin_release(silh_ctx* c) {
+  if (!c->pin) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.emplace_back(c->pin, c->pin_size);
+  c->pin = nullptr;
+  c->pin_size = c->pin_used = 0;
+}
+
+silh_status pin_acquire(silh_ctx* c, size_t min_bytes) {
+  pin_release(c);
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    for (size_t i = 0; i < g_pin_free.size(); ++i) {
+      if (g_pin_free[i].second >= min_bytes) {
+        c->pin = g_pin_free[i].first;
+        c->pin_size = g_pin_free[i].second;
+        g_pin_free.erase(g_pin_free.begin() + (long)i);
+        c->pin_used = 0;
+        return SILH_OK;
+      }
+    }
+  }
+  const size_t bytes = min_bytes > kPinBlock ? min_bytes : kPinBlock;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SILH_E_NOMEM, "pinned host allocation of %zu bytes failed", bytes);
+  }
+  c->pin = (unsigned char*)p;
+  c->pin_size = bytes;
+  c->pin_used = 0;
+  return SILH_OK;
+}
+
+// A slice of `bytes` for this context's next transfers (synchronises the
+// stream first when the block is full).
+silh_status stage(silh_ctx* c, size_t bytes, void** out) {
+  const size_t span = (bytes + 255) / 256 * 256;
+  if (c->pin && c->pin_used + span <= c->pin_size) {
+    *out = c->pin + c->pin_used;
+    c->pin_used += span;
+    return SILH_OK;
+  }
+  HIPCHK(hipStreamSynchronize(c->st));  // earlier slices are free again
+  c->pin_used = 0;
+  if (!c->pin || span > c->pin_size) CHK(pin_acquire(c, span));
+  *out = c->pin;
+  c->pin_used = span;
+  return SILH_OK;
+}
+
 template <class T>
 silh_status h2d(silh_ctx* c, T* dst, const std::vector<T>& src) {
   if (src.empty()) return SILH_OK;
-  HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->st));
+  void* p = nullptr;
+  CHK(stage(c, src.size() * sizeof(T), &p));
+  std::memcpy(p, src.data(), src.size() * sizeof(T));
+  HIPCHK(hipMemcpyAsync(dst, p, src.size() * sizeof(T), hipMemcpyHostToDevice, c->st));
+  return SILH_OK;
+}
+
+// Device-to-host read-backs: every part is copied through the staging block,
+// then the stream is synchronised and the values land in host memory.
+struct Fetch {
+  void* host;
+  const void* dev;
+  size_t bytes;
+};
+silh_status fetch(silh_ctx* c, std::initializer_list<Fetch> parts) {
+  size_t total = 0;
+  for (const Fetch& f : parts) total += (f.bytes + 255) / 256 * 256;
+  if (!c->pin || c->pin_used + total > c->pin_size) {
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->pin_used = 0;
+    if (!c->pin || total > c->pin_size) CHK(pin_acquire(c, total));
+  }
+  std::vector<void*> slots;
+  for (const Fetch& f : parts) {
+    void* p = nullptr;
+    CHK(stage(c, f.bytes, &p));
+    HIPCHK(hipMemcpyAsync(p, f.dev, f.bytes, hipMemcpyDeviceToHost, c->st));
+    slots.push_back(p);
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  size_t i = 0;
+  for (const Fetch& f : parts) std::memcpy(f.host, slots[i++], f.bytes);
+  c->pin_used = 0;  // every copy of this context is complete
   return SILH_OK;
 }
 
@@ -335,9 +433,7 @@ silh_status build_index(silh_ctx* c) {
     CHK(L.done());
   }
   c->counts_h.assign(k, 0u);
-  HIPCHK(hipMemcpyAsync(c->counts_h.data(), c->csize, k * sizeof(uint32_t), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipMemcpyAsync(&c->bad_h, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  CHK(fetch(c, {{c->counts_h.data(), c->csize, k * sizeof(uint32_t)}, {&c->bad_h, c->bad, sizeof(int)}}));
   if (c->bad_h) return fail(SILH_E_LABEL, "a label lies outside [0, %d)", k);
   c->csize_h.assign(k, 0);
   c->off_h.assign(k + 1, 0);
@@ -422,8 +518,7 @@ silh_status compact_and_pack(silh_ctx* c) {
   launch_gather_at(c->st, c->pos, c->off, k, c->s_off);
   HIPCHK(hipGetLastError());
   c->s_off32_h.assign(k + 1, 0);
-  HIPCHK(hipMemcpyAsync(c->s_off32_h.data(), c->s_off, (k + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  CHK(fetch(c, {{c->s_off32_h.data(), c->s_off, (k + 1) * sizeof(int32_t)}}));
   c->s_off_h.assign(k + 1, 0);
   c->cnt_h.assign(k, 0);
   c->sp_off_h.assign(k + 1, 0);
@@ -517,8 +612,7 @@ silh_status phase1(silh_ctx* c) {
     }
     launch_gather_at(c->st, c->pos, c->off, k, c->f0_off);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(c->f0_off32_h.data(), c->f0_off, (k + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    CHK(fetch(c, {{c->f0_off32_h.data(), c->f0_off, (k + 1) * sizeof(int32_t)}}));
     for (int j = 0; j <= k; ++j) c->f0_off_h[j] = c->f0_off32_h[j];
     c->F0 = c->f0_off_h[k];
   } else {
@@ -679,8 +773,7 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
       launch_mean(c->st, c->bpart, (int)ceil_div(c->n, c->p2_rows), c->n, c->mean_d);
       CHK(L.done());
     }
-    HIPCHK(hipMemcpyAsync(&c->mean_h, c->mean_d, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    CHK(fetch(c, {{&c->mean_h, c->mean_d, sizeof(double)}}));
     *mean_host = c->mean_h;
   }
   return SILH_OK;
@@ -718,9 +811,7 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   HIPCHK(hipGetLastError());
   int32_t mu_h = 0;
   int bad_h = 0;
-  HIPCHK(hipMemcpyAsync(&mu_h, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  CHK(fetch(c, {{&mu_h, pos + n, sizeof(int32_t)}, {&bad_h, bad, sizeof(int)}}));
   if (bad_h) return fail(SILH_E_ARG, "a row index lies outside [0, %d)", n);
   const int mu = mu_h;
   launch_rows_compact(c->st, mark, pos, n, urows);
@@ -762,8 +853,7 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   if (mean_host) {
     launch_mean(c->st, bpm, (int)nbm, m, mean_d);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&c->mean_h, mean_d, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    CHK(fetch(c, {{&c->mean_h, mean_d, sizeof(double)}}));
     *mean_host = c->mean_h;
   }
   return SILH_OK;
@@ -900,8 +990,7 @@ silh_status silh_coh_sep(silh_ctx* c, const float* W_hat, double* coh_host, doub
   launch_mean(c->st, spart, nb, 1, sums + 1);
   HIPCHK(hipGetLastError());
   double h[2] = {0.0, 0.0};
-  HIPCHK(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  CHK(fetch(c, {{h, sums, sizeof(h)}}));
   // denominators: unordered pairs inside clusters, and across clusters
   int64_t pin = 0, pout = 0, before = 0;
   for (int j = 0; j < k; ++j) {
@@ -996,6 +1085,7 @@ void silh_destroy(silh_ctx* c) {
   }
   c->pending.clear();
   return_events(c->pool);
+  pin_release(c);
   free_list(c, c->alloc_p2);
   free_list(c, c->alloc_rows);
   free_list(c, c->alloc_sample);
