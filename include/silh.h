@@ -286,8 +286,9 @@ silh_status silh_philox_uniform(uint64_t seed, int64_t gid0, int64_t count, uint
                                 double* out, silh_stream stream);
 
 /*
- * Kernel timing.  When enabled on a context, every kernel launch of that
- * context is bracketed by HIP events recorded on its stream; silh_prof_get
+ * Kernel timing.  on = 1: every kernel launch of the context is bracketed by
+ * HIP events recorded on its stream; on = 2: only the Phase-2 launches; 0:
+ * off (SILH_E_ARG outside [0, 2]).  silh_prof_get
  * returns, for kernel slot i (0 <= i < silh_prof_count), its name, the number
  * of timed launches and their total duration in milliseconds (this call
  * synchronises the stream).  silh_prof_reset clears the totals.

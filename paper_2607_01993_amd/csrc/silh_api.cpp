@@ -127,6 +127,7 @@ struct silh_ctx {
 
   // profiling
   bool prof_on = false;
+  int prof_mode = 1;  // 1: every kernel, 2: the Phase-2 launches only
   struct Pending {
     int slot;
     hipEvent_t a, b;
@@ -241,7 +242,7 @@ struct Launch {
   int slot;
   hipEvent_t a = nullptr;
   Launch(silh_ctx* ctx, int s) : c(ctx), slot(s) {
-    if (c->prof_on) {
+    if (c->prof_on && (c->prof_mode == 1 || s == K_PHASE2)) {
       a = get_event(c);
       if (a) (void)hipEventRecord(a, c->st);
     }
@@ -1050,7 +1051,9 @@ silh_status silh_philox_uniform(uint64_t seed, int64_t gid0, int64_t count, uint
 
 silh_status silh_prof_enable(silh_ctx* c, int on) {
   if (!c) return fail(SILH_E_ARG, "ctx is NULL");
+  if (on < 0 || on > 2) return fail(SILH_E_ARG, "profiling mode %d outside [0, 2]", on);
   c->prof_on = on != 0;
+  c->prof_mode = on;
   return SILH_OK;
 }
 

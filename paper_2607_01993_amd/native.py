@@ -482,7 +482,9 @@ def silh_philox_uniform(seed, gid0, count, stream_id, stream=None):
 
 
 def silh_prof_enable(ctx: Context, on=True):
-    _check(load_library().silh_prof_enable(ctx.ptr, 1 if on else 0), "silh_prof_enable")
+    """on: True / 1 = every kernel, 2 = the Phase-2 launches only, False / 0 = off."""
+    mode = int(on) if not isinstance(on, bool) else (1 if on else 0)
+    _check(load_library().silh_prof_enable(ctx.ptr, mode), "silh_prof_enable")
 
 
 def silh_prof_reset(ctx: Context):
