@@ -8,59 +8,41 @@
 namespace silh {
 
 // ----------------------------------------------------------------------------
-// cluster sizes + label validation
-// ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_count(const int32_t* __restrict__ labels, int n, int k,
-                                               uint32_t* __restrict__ counts, int* __restrict__ bad) {
-  extern __shared__ uint32_t hist[];
-  for (int j = threadIdx.x; j < k; j += blockDim.x) hist[j] = 0u;
-  __syncthreads();
-  int anybad = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int l = labels[i];
-    if (l < 0 || l >= k)
-      anybad = 1;
-    else
-      atomicAdd(&hist[l], 1u);
-  }
-  if (anybad) atomicOr(bad, 1);
-  __syncthreads();
-  for (int j = threadIdx.x; j < k; j += blockDim.x)
-    if (hist[j]) atomicAdd(&counts[j], hist[j]);
-}
-
-void launch_count(hipStream_t st, const int32_t* labels, int n, int k, uint32_t* counts, int* bad) {
-  int blocks = (int)ceil_div(n, 256);
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), k * sizeof(uint32_t), st, labels, n, k,
-                     counts, bad);
-}
-
-// ----------------------------------------------------------------------------
 // stable counting sort by label: per-unit histograms, per-label scan over
 // units, then an in-order scatter with one wave per unit
 // ----------------------------------------------------------------------------
+// Per-unit label histograms; a label outside [0, k) is not counted and sets
+// *bad (the cluster sizes are then not used).
 __global__ __launch_bounds__(64) void k_unit_hist(const int32_t* __restrict__ labels, int n, int k,
-                                                  int32_t* __restrict__ uh) {
+                                                  int32_t* __restrict__ uh, int* __restrict__ bad) {
   extern __shared__ int32_t h[];
   for (int j = threadIdx.x; j < k; j += 64) h[j] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortSeg;
   const int64_t end = base + kSortSeg < n ? base + kSortSeg : n;
-  for (int64_t i = base + threadIdx.x; i < end; i += 64) atomicAdd(&h[labels[i]], 1);
+  int anybad = 0;
+  for (int64_t i = base + threadIdx.x; i < end; i += 64) {
+    const int l = labels[i];
+    if ((unsigned)l < (unsigned)k)
+      atomicAdd(&h[l], 1);
+    else
+      anybad = 1;
+  }
+  if (anybad) atomicOr(bad, 1);
   __syncthreads();
   int32_t* row = uh + (size_t)blockIdx.x * k;
   for (int j = threadIdx.x; j < k; j += 64) row[j] = h[j];
 }
 
-void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh) {
+void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh, int* bad) {
   const int units = (int)ceil_div(n, kSortSeg);
-  hipLaunchKernelGGL(k_unit_hist, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, uh);
+  hipLaunchKernelGGL(k_unit_hist, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, uh, bad);
 }
 
-// one block per label: uh[u][j] <- off[j] + sum_{u' < u} uh[u'][j]
+// one block per label: uh[u][j] <- sum_{u' < u} uh[u'][j] (the label's rows
+// before unit u), and counts[j] = the label's total (the cluster size)
 __global__ __launch_bounds__(256) void k_unit_scan(int32_t* __restrict__ uh, int units, int k,
-                                                   const int32_t* __restrict__ off) {
+                                                   int32_t* __restrict__ counts) {
   __shared__ int32_t part[256];
   const int j = blockIdx.x;
   const int per = (units + 255) / 256;
@@ -77,16 +59,17 @@ __global__ __launch_bounds__(256) void k_unit_scan(int32_t* __restrict__ uh, int
     part[threadIdx.x] += v;
     __syncthreads();
   }
-  int32_t run = off[j] + (threadIdx.x ? part[threadIdx.x - 1] : 0);
+  int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
   for (int u = u0; u < u1; ++u) {
     const int32_t v = uh[(size_t)u * k + j];
     uh[(size_t)u * k + j] = run;
     run += v;
   }
+  if (threadIdx.x == 255) counts[j] = part[255];
 }
 
-void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, const int32_t* off) {
-  hipLaunchKernelGGL(k_unit_scan, dim3(k), dim3(256), 0, st, uh, units, k, off);
+void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* counts) {
+  hipLaunchKernelGGL(k_unit_scan, dim3(k), dim3(256), 0, st, uh, units, k, counts);
 }
 
 // One wave per unit walks its rows in order, 64 at a time.  Lanes holding the
@@ -94,11 +77,12 @@ void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, const int32
 // output is stable: ids ascend inside each cluster.
 __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labels, int n, int k,
                                                 const int32_t* __restrict__ ubase,
+                                                const int32_t* __restrict__ off,
                                                 int32_t* __restrict__ perm, int32_t* __restrict__ slab) {
   extern __shared__ int32_t run[];
   const int lane = threadIdx.x;
   const int32_t* row = ubase + (size_t)blockIdx.x * k;
-  for (int j = lane; j < k; j += 64) run[j] = row[j];
+  for (int j = lane; j < k; j += 64) run[j] = off[j] + row[j];
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortSeg;
   const int64_t end = base + kSortSeg < n ? base + kSortSeg : n;
@@ -127,9 +111,9 @@ __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labe
 }
 
 void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, const int32_t* ubase,
-                    int32_t* perm, int32_t* slab) {
+                    const int32_t* off, int32_t* perm, int32_t* slab) {
   const int units = (int)ceil_div(n, kSortSeg);
-  hipLaunchKernelGGL(k_scatter, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, ubase,
+  hipLaunchKernelGGL(k_scatter, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, ubase, off,
                      perm, slab);
 }
 

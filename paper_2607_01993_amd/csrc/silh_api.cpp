@@ -48,8 +48,7 @@ silh_status fail(silh_status st, const char* fmt, ...) {
   } while (0)
 
 enum Slot {
-  K_COUNT = 0,
-  K_SORT_HIST,
+  K_SORT_HIST = 0,
   K_SORT_SCAN,
   K_SORT_SCATTER,
   K_F0_FLAG,
@@ -66,7 +65,7 @@ enum Slot {
   K_NSLOTS
 };
 const char* const kSlotNames[K_NSLOTS] = {
-    "count",   "sort_hist", "sort_scan", "sort_scatter", "f0_flag", "scan", "f0_pack",
+    "sort_hist", "sort_scan", "sort_scatter", "f0_flag", "scan", "f0_pack",
     "w_partial", "w_final", "draw",      "pack",         "center",  "pack_mfma", "phase2", "mean"};
 
 constexpr int64_t kMaxN = (int64_t)1 << 30;
@@ -426,11 +425,16 @@ silh_status build_index(silh_ctx* c) {
     cv.add(&c->uh, (size_t)units * k).add(&c->perm, (size_t)n).add(&c->slab, (size_t)n);
     CHK(cv.commit(c, c->alloc_init));
   }
-  HIPCHK(hipMemsetAsync(c->csize, 0, (size_t)k * sizeof(int32_t), c->st));
   HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
+  // cluster sizes from the sort's per-unit histograms (no separate count pass)
   {
-    Launch L(c, K_COUNT);
-    launch_count(c->st, c->labels, n, k, (uint32_t*)c->csize, c->bad);
+    Launch L(c, K_SORT_HIST);
+    launch_unit_hist(c->st, c->labels, n, k, c->uh, c->bad);
+    CHK(L.done());
+  }
+  {
+    Launch L(c, K_SORT_SCAN);
+    launch_unit_scan(c->st, c->uh, units, k, c->csize);
     CHK(L.done());
   }
   c->counts_h.assign(k, 0u);
@@ -458,18 +462,8 @@ silh_status build_index(silh_ctx* c) {
   CHK(h2d(c, c->off, c->off_h));
   CHK(h2d(c, c->q, c->q_h));
   {
-    Launch L(c, K_SORT_HIST);
-    launch_unit_hist(c->st, c->labels, n, k, c->uh);
-    CHK(L.done());
-  }
-  {
-    Launch L(c, K_SORT_SCAN);
-    launch_unit_scan(c->st, c->uh, units, k, c->off);
-    CHK(L.done());
-  }
-  {
     Launch L(c, K_SORT_SCATTER);
-    launch_scatter(c->st, c->labels, n, k, c->uh, c->perm, c->slab);
+    launch_scatter(c->st, c->labels, n, k, c->uh, c->off, c->perm, c->slab);
     CHK(L.done());
   }
   return SILH_OK;

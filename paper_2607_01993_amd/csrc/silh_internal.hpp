@@ -21,11 +21,13 @@ constexpr int kP2Rows = 256;
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- cluster index -------------------------------------------------------
-void launch_count(hipStream_t st, const int32_t* labels, int n, int k, uint32_t* counts, int* bad);
-void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh);
-void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, const int32_t* off);
+// per-unit label histograms uh [units][k]; *bad = 1 if a label is outside [0, k)
+void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh, int* bad);
+// uh[u][j] <- label j's rows before unit u; counts[j] = |C_j|
+void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* counts);
+// stable scatter: rows of label j go to off[j] + uh[u][j] + (rank inside the unit)
 void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, const int32_t* ubase,
-                    int32_t* perm, int32_t* slab);
+                    const int32_t* off, int32_t* perm, int32_t* slab);
 // out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.  tmp holds
 // ceil_div(n, kScanTile) + 1 ints.
 void launch_scan(hipStream_t st, const int32_t* in, int n, int32_t* out, int32_t* tmp);
