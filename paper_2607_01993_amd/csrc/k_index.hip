@@ -13,13 +13,13 @@ namespace silh {
 // ----------------------------------------------------------------------------
 // Per-unit label histograms; a label outside [0, k) is not counted and sets
 // *bad (the cluster sizes are then not used).
-__global__ __launch_bounds__(64) void k_unit_hist(const int32_t* __restrict__ labels, int n, int k,
+__global__ __launch_bounds__(64) void k_unit_hist(const int32_t* __restrict__ labels, int n, int k, int seg,
                                                   int32_t* __restrict__ uh, int* __restrict__ bad) {
   extern __shared__ int32_t h[];
   for (int j = threadIdx.x; j < k; j += 64) h[j] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortSeg;
-  const int64_t end = base + kSortSeg < n ? base + kSortSeg : n;
+  const int64_t base = (int64_t)blockIdx.x * seg;
+  const int64_t end = base + seg < n ? base + seg : n;
   int anybad = 0;
   for (int64_t i = base + threadIdx.x; i < end; i += 64) {
     const int l = labels[i];
@@ -30,13 +30,13 @@ __global__ __launch_bounds__(64) void k_unit_hist(const int32_t* __restrict__ la
   }
   if (anybad) atomicOr(bad, 1);
   __syncthreads();
-  int32_t* row = uh + (size_t)blockIdx.x * k;
-  for (int j = threadIdx.x; j < k; j += 64) row[j] = h[j];
+  const int units = gridDim.x;  // label-major [k][units]: each label's scan reads one row
+  for (int j = threadIdx.x; j < k; j += 64) uh[(size_t)j * units + blockIdx.x] = h[j];
 }
 
-void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh, int* bad) {
-  const int units = (int)ceil_div(n, kSortSeg);
-  hipLaunchKernelGGL(k_unit_hist, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, uh, bad);
+void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int seg, int32_t* uh, int* bad) {
+  const int units = (int)ceil_div(n, seg);
+  hipLaunchKernelGGL(k_unit_hist, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, seg, uh, bad);
 }
 
 // one block per label: uh[u][j] <- sum_{u' < u} uh[u'][j] (the label's rows
@@ -48,8 +48,9 @@ __global__ __launch_bounds__(256) void k_unit_scan(int32_t* __restrict__ uh, int
   const int per = (units + 255) / 256;
   const int u0 = threadIdx.x * per;
   const int u1 = u0 + per < units ? u0 + per : units;
+  int32_t* row = uh + (size_t)j * units;
   int32_t s = 0;
-  for (int u = u0; u < u1; ++u) s += uh[(size_t)u * k + j];
+  for (int u = u0; u < u1; ++u) s += row[u];
   part[threadIdx.x] = s;
   __syncthreads();
   // inclusive Hillis-Steele scan over the 256 partial sums
@@ -61,8 +62,8 @@ __global__ __launch_bounds__(256) void k_unit_scan(int32_t* __restrict__ uh, int
   }
   int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
   for (int u = u0; u < u1; ++u) {
-    const int32_t v = uh[(size_t)u * k + j];
-    uh[(size_t)u * k + j] = run;
+    const int32_t v = row[u];
+    row[u] = run;
     run += v;
   }
   if (threadIdx.x == 255) counts[j] = part[255];
@@ -73,48 +74,99 @@ void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* co
 }
 
 // One wave per unit walks its rows in order, 64 at a time.  Lanes holding the
-// same label get consecutive slots in lane order (ballot + popcount), so the
-// output is stable: ids ascend inside each cluster.
-__global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labels, int n, int k,
+// same label get consecutive ranks in lane order (ballot + popcount), so the
+// order is stable: ids ascend inside each cluster.  The unit's rows are first
+// placed in LDS grouped by label (the unit's own label offsets), then each
+// label's run is written to its global range in one contiguous piece.
+// LDS: base[k] (global start of the unit's run of label j), loc[k] (next local
+// slot of label j), ids[seg], lab[seg].
+__global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labels, int n, int k, int seg,
                                                 const int32_t* __restrict__ ubase,
                                                 const int32_t* __restrict__ off,
                                                 int32_t* __restrict__ perm, int32_t* __restrict__ slab) {
-  extern __shared__ int32_t run[];
+  extern __shared__ int32_t lds[];
+  int32_t* base = lds;
+  int32_t* loc = lds + k;
+  int32_t* ids = lds + 2 * k;
+  int32_t* lab = ids + seg;
   const int lane = threadIdx.x;
-  const int32_t* row = ubase + (size_t)blockIdx.x * k;
-  for (int j = lane; j < k; j += 64) run[j] = off[j] + row[j];
+  const int u = blockIdx.x;
+  const int units = (int)(((int64_t)n + seg - 1) / seg);
+  const int64_t b0 = (int64_t)u * seg;
+  const int64_t end = b0 + seg < n ? b0 + seg : n;
+  const int cntu = (int)(end - b0);
+  // the unit's own count of label j: next unit's prefix minus this one's (the
+  // last unit: the cluster size, off[j + 1] - off[j], minus its prefix)
+  // ubase is label-major: ubase[j * units + u]
+  for (int j = lane; j < k; j += 64) {
+    const int32_t cur = ubase[(size_t)j * units + u];
+    const int32_t nxt = u + 1 < units ? ubase[(size_t)j * units + u + 1] : off[j + 1] - off[j];
+    base[j] = off[j] + cur;
+    loc[j] = nxt - cur;  // count, turned into the local offset below
+  }
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortSeg;
-  const int64_t end = base + kSortSeg < n ? base + kSortSeg : n;
+  // exclusive scan of the unit's label counts (64 lanes, k / 64 each)
+  {
+    const int per = (k + 63) / 64;
+    const int j0 = lane * per;
+    const int j1 = j0 + per < k ? j0 + per : k;
+    int32_t sum = 0;
+    for (int j = j0; j < j1; ++j) sum += loc[j];
+    int32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    int32_t run = incl - sum;
+    for (int j = j0; j < j1; ++j) {
+      const int32_t c = loc[j];
+      loc[j] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t c = base; c < end; c += 64) {
+  for (int64_t c = b0; c < end; c += 64) {
     const int64_t i = c + lane;
     const bool valid = i < end;
-    const int lab = valid ? labels[i] : -1;
+    const int L = valid ? labels[i] : -1;
     uint64_t active = __ballot(valid);
     while (active) {
       const int leader = __ffsll((unsigned long long)active) - 1;
-      const int L = __shfl(lab, leader, 64);
-      const uint64_t mask = __ballot(valid && lab == L);
-      int32_t slot = 0;
-      if (valid && lab == L) {
-        slot = run[L] + __popcll(mask & lt);
-        perm[slot] = (int32_t)i;
-        slab[slot] = L;
+      const int Ll = __shfl(L, leader, 64);
+      const uint64_t mask = __ballot(valid && L == Ll);
+      if (valid && L == Ll) {
+        const int slot = loc[Ll] + __popcll(mask & lt);
+        ids[slot] = (int32_t)i;
+        lab[slot] = Ll;
       }
       __syncthreads();
-      if (lane == leader) run[L] += __popcll(mask);
+      if (lane == leader) loc[Ll] += __popcll(mask);
       __syncthreads();
       active &= ~mask;
     }
   }
+  __syncthreads();
+  // loc[j] is now the end of label j's local run; its start is loc[j] - count.
+  // Local slot p of label j goes to base[j] + (p - start_j): runs of one label
+  // are consecutive in both places, so the writes are contiguous.
+  for (int p = lane; p < cntu; p += 64) {
+    const int Lp = lab[p];
+    const int32_t cur = ubase[(size_t)Lp * units + u];
+    const int32_t nxt = u + 1 < units ? ubase[(size_t)Lp * units + u + 1] : off[Lp + 1] - off[Lp];
+    const int32_t start = loc[Lp] - (nxt - cur);
+    const int32_t g = base[Lp] + (p - start);
+    perm[g] = ids[p];
+    slab[g] = Lp;
+  }
 }
 
-void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, const int32_t* ubase,
+void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, int seg, const int32_t* ubase,
                     const int32_t* off, int32_t* perm, int32_t* slab) {
-  const int units = (int)ceil_div(n, kSortSeg);
-  hipLaunchKernelGGL(k_scatter, dim3(units), dim3(64), k * sizeof(int32_t), st, labels, n, k, ubase, off,
-                     perm, slab);
+  const int units = (int)ceil_div(n, seg);
+  const size_t lds = (size_t)(2 * k + 2 * seg) * sizeof(int32_t);
+  hipLaunchKernelGGL(k_scatter, dim3(units), dim3(64), lds, st, labels, n, k, seg, ubase, off, perm, slab);
 }
 
 // ----------------------------------------------------------------------------

@@ -418,7 +418,8 @@ silh_status check_params(const silh_params* prm, const float* X, const int32_t* 
 // Cluster sizes, offsets and the stable sort by label.
 silh_status build_index(silh_ctx* c) {
   const int n = c->n, k = c->k;
-  const int units = (int)ceil_div(n, kSortSeg);
+  const int seg = sort_seg(n, k);
+  const int units = (int)ceil_div(n, seg);
   {
     Carve cv;
     cv.add(&c->csize, (size_t)k).add(&c->bad, 1).add(&c->off, (size_t)k + 1).add(&c->q, (size_t)k);
@@ -429,7 +430,7 @@ silh_status build_index(silh_ctx* c) {
   // cluster sizes from the sort's per-unit histograms (no separate count pass)
   {
     Launch L(c, K_SORT_HIST);
-    launch_unit_hist(c->st, c->labels, n, k, c->uh, c->bad);
+    launch_unit_hist(c->st, c->labels, n, k, seg, c->uh, c->bad);
     CHK(L.done());
   }
   {
@@ -463,7 +464,7 @@ silh_status build_index(silh_ctx* c) {
   CHK(h2d(c, c->q, c->q_h));
   {
     Launch L(c, K_SORT_SCATTER);
-    launch_scatter(c->st, c->labels, n, k, c->uh, c->off, c->perm, c->slab);
+    launch_scatter(c->st, c->labels, n, k, seg, c->uh, c->off, c->perm, c->slab);
     CHK(L.done());
   }
   return SILH_OK;

@@ -6,8 +6,11 @@
 
 namespace silh {
 
-// Rows per unit of the stable counting sort (one wave per unit).
-constexpr int kSortSeg = 1024;
+// Rows per unit of the stable counting sort (one wave per unit): 256 while the
+// per-unit histograms (units x k ints) stay small, else 1024.
+inline int sort_seg(int64_t n, int k) {
+  return (n + 255) / 256 * (int64_t)k <= ((int64_t)1 << 26) ? 256 : 1024;
+}
 // Elements per block of the int32 exclusive scan (256 threads x 8).
 constexpr int kScanTile = 2048;
 // Members per work item of the W(e_bar) partial sums.
@@ -21,12 +24,12 @@ constexpr int kP2Rows = 256;
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- cluster index -------------------------------------------------------
-// per-unit label histograms uh [units][k]; *bad = 1 if a label is outside [0, k)
-void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int32_t* uh, int* bad);
+// per-unit label histograms uh [k][units] (label-major); *bad = 1 if a label is outside [0, k)
+void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int seg, int32_t* uh, int* bad);
 // uh[u][j] <- label j's rows before unit u; counts[j] = |C_j|
 void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* counts);
 // stable scatter: rows of label j go to off[j] + uh[u][j] + (rank inside the unit)
-void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, const int32_t* ubase,
+void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, int seg, const int32_t* ubase,
                     const int32_t* off, int32_t* perm, int32_t* slab);
 // out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.  tmp holds
 // ceil_div(n, kScanTile) + 1 ints.
