@@ -297,6 +297,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, int byt
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
 }
 
+// V consecutive row elements from c on, zero from lim on.  With vec (rows
+// V-float aligned and c a multiple of V) the chunk is one vector load and lies
+// wholly inside or outside [0, lim); otherwise element by element.  Loads go
+// to a clamped address and the value is selected, so no load is predicated.
+template <int V>
+__device__ __forceinline__ void load_chunk(const float* __restrict__ xp, int c, int lim, bool vec,
+                                           float (&out)[V]) {
+  typedef float fvec __attribute__((ext_vector_type(V)));
+  if (vec) {
+    const bool in = c < lim;
+    const fvec t = *(const fvec*)(xp + (in ? c : 0));
+#pragma unroll
+    for (int e = 0; e < V; ++e) out[e] = in ? t[e] : 0.0f;
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const bool in = c + e < lim;
+      const float t = xp[in ? c + e : 0];
+      out[e] = in ? t : 0.0f;
+    }
+  }
+}
+
 // one tile's B operand (this lane's half row), weight and element id (the
 // fp8 path loads the sample's norm term instead of the id)
 template <int P, int DM>
@@ -372,11 +395,16 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   const int rr = (lane >> 1) & 15;
   const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
 
-  // this lane's half of its A rows (raw or unit-scaled), zero outside [0, d).
-  // Long rows are not kept: they are re-read per cluster (L2) and rescaled.
-  constexpr bool kKeepX = C::HALF <= 40;
+  // this lane's half of its A rows (raw or unit-scaled), zero outside [0, d),
+  // resident for the whole cluster loop (at d = 256 partly in AGPRs, which
+  // the one wave per SIMD that the tile registers allow leaves free);
+  // re-reading it per cluster would stream X k times through L2.
+  // Rows and centres are read in V-float chunks (h * HALF is a multiple of V).
+  constexpr int V = C::HALF % 4 == 0 ? 4 : 2;
+  typedef float fvec __attribute__((ext_vector_type(V)));
+  const bool vec = d % V == 0 && ((uintptr_t)X & (4 * V - 1)) == 0;
   float xr[PB][C::HALF];
-  float ux[PB], rxs[PB];
+  float ux[PB];
   int pout[PB], own[PB];
   double w_own[PB], bmin[PB];
 #pragma unroll
@@ -384,21 +412,22 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     const int pb = P0 + 32 * b + col;
     const int pa = pb < n ? pb : n - 1;
     const float* xp = X + (size_t)pa * d;
+    float p = 0.f;
 #pragma unroll
-    for (int i = 0; i < C::HALF; ++i) {
-      const int c = h * C::HALF + i;
-      xr[b][i] = (c < DM && c < d) ? xp[c] : 0.0f;
+    for (int i0 = 0; i0 < C::HALF; i0 += V) {
+      float xc[V];
+      load_chunk<V>(xp, h * C::HALF + i0, d, vec, xc);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        xr[b][i0 + e] = xc[e];
+        p = fmaf(xc[e], xc[e], p);
+      }
     }
     ux[b] = 0.f;
-    rxs[b] = 1.f;
     if (M == kCos) {
-      float p = 0.f;
-#pragma unroll
-      for (int i = 0; i < C::HALF; ++i) p = fmaf(xr[b][i], xr[b][i], p);
       const float s2 = p + __shfl_xor(p, 32, kWave);
       const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
       ux[b] = s2 > 0.f ? 0.f : 0.5f;
-      rxs[b] = rx;
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
     }
@@ -413,130 +442,65 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   for (int j = 0; j < k; ++j) {
     // ---- A operands for cluster j: x~ = x - mu_j (mu zero-padded to KP),
     // rounded to the input precision, plus the augmentation
-    if constexpr (kKeepX) {
-      const float* m = mu + (size_t)j * C::KP + h * C::HALF;
-      float mv[C::HALF];
+    const float* m = mu + (size_t)j * C::KP + h * C::HALF;  // 16-byte aligned rows
+    float mv[C::HALF];
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) mv[i] = m[i];
+    for (int i0 = 0; i0 < C::HALF; i0 += V) {
+      const fvec t = *(const fvec*)(m + i0);
 #pragma unroll
-      for (int b = 0; b < PB; ++b) {
-        float xq[C::HALF];
-        float part = 0.f;
-        if constexpr (P == 2) {
+      for (int e = 0; e < V; ++e) mv[i0 + e] = t[e];
+    }
 #pragma unroll
-          for (int i = 0; i < C::HALF; ++i) {
-            const float q = q_fp8(kFp8Scale * (xr[b][i] - mv[i]));
-            const float v = q * (1.0f / kFp8Scale);
-            xq[i] = q;
-            part = fmaf(v, v, part);
-          }
-          const float rowv = S2 * fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
-          // the C rows of this lane are elements 8(r/4) + 4h + r%4 of the block
-#pragma unroll
-          for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
-#pragma unroll
-          for (int s = 0; s < C::NSTEP; ++s)
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              A[b].v[s][e] = fp8_pack4(xq[32 * s + 4 * e], xq[32 * s + 4 * e + 1], xq[32 * s + 4 * e + 2],
-                                       xq[32 * s + 4 * e + 3]);
-          continue;
-        }
+    for (int b = 0; b < PB; ++b) {
+      float xq[C::HALF];
+      float part = 0.f;
+      if constexpr (P == 2) {
 #pragma unroll
         for (int i = 0; i < C::HALF; ++i) {
-          float v = xr[b][i] - mv[i];
-          if (P == 1) v = q_bf16(v);
-          xq[i] = v;
+          const float q = q_fp8(kFp8Scale * (xr[b][i] - mv[i]));
+          const float v = q * (1.0f / kFp8Scale);
+          xq[i] = q;
           part = fmaf(v, v, part);
         }
-        const float nx = part + __shfl_xor(part, 32, kWave);
-        const float an = fmaf(alpha, nx, ux[b]);
-        float aug[C::AUG > 0 ? C::AUG : 1];
-        if constexpr (P == 0) {
-          aug[0] = an;
-          aug[1] = 1.0f;
-        } else if constexpr (P == 1) {
-          split3(an, aug[0], aug[1], aug[2]);
-          aug[3] = aug[4] = aug[5] = 1.0f;
-        }
+        const float rowv = S2 * fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
+        // the C rows of this lane are elements 8(r/4) + 4h + r%4 of the block
 #pragma unroll
-        for (int q = 0; q < C::AUG; ++q) xq[AUG0 + q] = h ? aug[q] : xq[AUG0 + q];
-        if constexpr (P == 0) {
+        for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
 #pragma unroll
-          for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
-        } else if constexpr (P == 1) {
+        for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
-          for (int s = 0; s < C::NSTEP; ++s)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)xq[8 * s + e];
-        }
+          for (int e = 0; e < 8; ++e)
+            A[b].v[s][e] = fp8_pack4(xq[32 * s + 4 * e], xq[32 * s + 4 * e + 1], xq[32 * s + 4 * e + 2],
+                                     xq[32 * s + 4 * e + 3]);
+        continue;
       }
-    } else {
-      // long rows: built step by step from the row (re-read) and the centre
-      const float* m = mu + (size_t)j * C::KP + h * C::HALF;
-      constexpr int E = P == 0 ? 1 : (P == 1 ? 8 : 32);   // elements per MFMA step
 #pragma unroll
-      for (int b = 0; b < PB; ++b) {
-        const int pb = P0 + 32 * b + col;
-        const float* xp = X + (size_t)(pb < n ? pb : n - 1) * d;
-        float part = 0.f;
+      for (int i = 0; i < C::HALF; ++i) {
+        float v = xr[b][i] - mv[i];
+        if (P == 1) v = q_bf16(v);
+        xq[i] = v;
+        part = fmaf(v, v, part);
+      }
+      const float nx = part + __shfl_xor(part, 32, kWave);
+      const float an = fmaf(alpha, nx, ux[b]);
+      float aug[C::AUG > 0 ? C::AUG : 1];
+      if constexpr (P == 0) {
+        aug[0] = an;
+        aug[1] = 1.0f;
+      } else if constexpr (P == 1) {
+        split3(an, aug[0], aug[1], aug[2]);
+        aug[3] = aug[4] = aug[5] = 1.0f;
+      }
 #pragma unroll
-        for (int s = 0; s < C::NSTEP; ++s) {
-          float q[E];
+      for (int q = 0; q < C::AUG; ++q) xq[AUG0 + q] = h ? aug[q] : xq[AUG0 + q];
+      if constexpr (P == 0) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const int i = s * E + e;
-            const int c = h * C::HALF + i;
-            const float xv = (c < DM && c < d) ? xp[c] * rxs[b] : 0.0f;
-            float v = xv - m[i];
-            if (P == 2) {
-              v = q_fp8(kFp8Scale * v);
-              const float dq = v * (1.0f / kFp8Scale);
-              part = fmaf(dq, dq, part);
-            } else {
-              if (P == 1) v = q_bf16(v);
-              part = fmaf(v, v, part);
-            }
-            q[e] = v;
-          }
-          if constexpr (P == 0) {
-            A[b].v[s] = q[0];
-          } else if constexpr (P == 1) {
+        for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
+      } else if constexpr (P == 1) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)q[e];
-          } else {
+        for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) A[b].v[s][e] = fp8_pack4(q[4 * e], q[4 * e + 1], q[4 * e + 2], q[4 * e + 3]);
-          }
-        }
-        const float nx = part + __shfl_xor(part, 32, kWave);
-        const float an = fmaf(alpha, nx, ux[b]);
-        if constexpr (P == 2) {
-          const float rowv = S2 * an;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
-        } else {
-          float aug[C::AUG > 0 ? C::AUG : 1];
-          if constexpr (P == 0) {
-            aug[0] = an;
-            aug[1] = 1.0f;
-          } else {
-            split3(an, aug[0], aug[1], aug[2]);
-            aug[3] = aug[4] = aug[5] = 1.0f;
-          }
-#pragma unroll
-          for (int q2 = 0; q2 < C::AUG; ++q2) {
-            constexpr int dummy = 0;
-            (void)dummy;
-            const int i = AUG0 + q2;
-            if constexpr (P == 0) {
-              A[b].v[i] = h ? aug[q2] : A[b].v[i];
-            } else {
-              const __bf16 cur = A[b].v[i / 8][i % 8];
-              A[b].v[i / 8][i % 8] = h ? (__bf16)aug[q2] : cur;
-            }
-          }
-        }
+          for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)xq[8 * s + e];
       }
     }
 
@@ -737,7 +701,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
 // below is the measured choice on the benchmark workload; the autotuner may
 // pick per (metric, operands, d, sample size).  fp8 always uses one.
 int mfma_pb_default(int prec, int DM) { return (prec == 0 && DM <= 32) ? 2 : 1; }
-int mfma_pb_max(int prec, int DM) { return (prec == 2 || DM > 128) ? 1 : 2; }
+int mfma_pb_max(int prec, int DM) { return (prec == 2 || DM > 64) ? 1 : 2; }
 
 template <int M, int P, int DM, int PB>
 static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
@@ -751,7 +715,7 @@ static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, con
 template <int M, int P, int DM>
 static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
                             const float* bnorm, int pb) {
-  if constexpr (P != 2 && DM <= 128) {  // two blocks per wave would not fit the registers beyond
+  if constexpr (P != 2 && DM <= 64) {  // two blocks per wave would not fit the registers beyond
     if (pb == 2) {
       launch_mfma_pb<M, P, DM, 2>(st, A, mu, Ym, bnorm);
       return;
