@@ -28,6 +28,9 @@ SOURCES = {
     "k_phase2_valu.hip": [],
     "k_rows.hip": [],
     "k_cohsep.hip": [],
+    "silh_graph.cpp": [],
+    # the sizes computed here repeat the host's floating-point steps exactly
+    "k_graph.hip": ["-ffp-contract=off"],
     # MFMA results straight into VGPRs (no accumulator-register copies)
     "k_phase2_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }

@@ -79,7 +79,8 @@ void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* co
 // placed in LDS grouped by label (the unit's own label offsets), then each
 // label's run is written to its global range in one contiguous piece.
 // LDS: base[k] (global start of the unit's run of label j), loc[k] (next local
-// slot of label j), ids[seg], lab[seg].
+// slot of label j), ids[seg], lab[seg].  A label outside [0, k) (already
+// flagged by k_unit_hist) is skipped, so no access leaves the arrays.
 __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labels, int n, int k, int seg,
                                                 const int32_t* __restrict__ ubase,
                                                 const int32_t* __restrict__ off,
@@ -94,7 +95,6 @@ __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labe
   const int units = (int)(((int64_t)n + seg - 1) / seg);
   const int64_t b0 = (int64_t)u * seg;
   const int64_t end = b0 + seg < n ? b0 + seg : n;
-  const int cntu = (int)(end - b0);
   // the unit's own count of label j: next unit's prefix minus this one's (the
   // last unit: the cluster size, off[j + 1] - off[j], minus its prefix)
   // ubase is label-major: ubase[j * units + u]
@@ -106,6 +106,7 @@ __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labe
   }
   __syncthreads();
   // exclusive scan of the unit's label counts (64 lanes, k / 64 each)
+  int nvalid = 0;
   {
     const int per = (k + 63) / 64;
     const int j0 = lane * per;
@@ -124,13 +125,14 @@ __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labe
       loc[j] = run;
       run += c;
     }
+    nvalid = __shfl(incl, 63, 64);  // rows of the unit with a label in [0, k)
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t c = b0; c < end; c += 64) {
     const int64_t i = c + lane;
-    const bool valid = i < end;
-    const int L = valid ? labels[i] : -1;
+    const int L = i < end ? labels[i] : -1;
+    const bool valid = (unsigned)L < (unsigned)k;
     uint64_t active = __ballot(valid);
     while (active) {
       const int leader = __ffsll((unsigned long long)active) - 1;
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labe
   // loc[j] is now the end of label j's local run; its start is loc[j] - count.
   // Local slot p of label j goes to base[j] + (p - start_j): runs of one label
   // are consecutive in both places, so the writes are contiguous.
-  for (int p = lane; p < cntu; p += 64) {
+  for (int p = lane; p < nvalid; p += 64) {
     const int Lp = lab[p];
     const int32_t cur = ubase[(size_t)Lp * units + u];
     const int32_t nxt = u + 1 < units ? ubase[(size_t)Lp * units + u + 1] : off[Lp + 1] - off[Lp];

@@ -141,11 +141,12 @@ __global__ __launch_bounds__(256) void k_f0_pack(const int32_t* __restrict__ per
                                                  const int32_t* __restrict__ flag,
                                                  const int32_t* __restrict__ pos, int n,
                                                  const float* __restrict__ X, int d, int DM,
-                                                 int64_t* __restrict__ f0_gid,
+                                                 int cap, int64_t* __restrict__ f0_gid,
                                                  int32_t* __restrict__ f0_cl, double* __restrict__ f0X) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !flag[i]) return;
   const int dst = pos[i];
+  if (dst >= cap) return;  // capacity of f0_gid / f0_cl / f0X rows
   const int g = perm[i];
   f0_gid[dst] = g;
   f0_cl[dst] = slab[i];
@@ -155,10 +156,10 @@ __global__ __launch_bounds__(256) void k_f0_pack(const int32_t* __restrict__ per
 }
 
 void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
-                    const int32_t* pos, int n, const float* X, int d, int DM, int64_t* f0_gid,
+                    const int32_t* pos, int n, const float* X, int d, int DM, int cap, int64_t* f0_gid,
                     int32_t* f0_cl, double* f0X) {
   hipLaunchKernelGGL(k_f0_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos,
-                     n, X, d, DM, f0_gid, f0_cl, f0X);
+                     n, X, d, DM, cap, f0_gid, f0_cl, f0X);
 }
 
 // ----------------------------------------------------------------------------
@@ -273,9 +274,10 @@ void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, 
 }
 
 // W(e_bar): sum of its cluster's item partials.  One block per initial
-// element; threads take items in a fixed stride, then a fixed-order block sum.
+// element (blocks past f0_off[k], the size of F0, return at once); threads
+// take items in a fixed stride, then a fixed-order block sum.
 __global__ __launch_bounds__(256) void k_w_final(const int32_t* __restrict__ f0_cl,
-                                                 const int32_t* __restrict__ f0_off,
+                                                 const int32_t* __restrict__ f0_off, int k,
                                                  const int32_t* __restrict__ citem_first,
                                                  const int32_t* __restrict__ citem_count,
                                                  const int32_t* __restrict__ items,
@@ -283,6 +285,7 @@ __global__ __launch_bounds__(256) void k_w_final(const int32_t* __restrict__ f0_
                                                  double* __restrict__ W) {
   __shared__ double sh[4];
   const int i = blockIdx.x;
+  if (i >= f0_off[k]) return;
   const int j = f0_cl[i];
   const int local = i - f0_off[j];
   const int first = citem_first[j], cnt = citem_count[j];
@@ -292,11 +295,11 @@ __global__ __launch_bounds__(256) void k_w_final(const int32_t* __restrict__ f0_
   if (threadIdx.x == 0) W[i] = tot;
 }
 
-void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off,
+void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off, int k,
                     const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
                     const double* partial, double* W) {
   if (F0 <= 0) return;
-  hipLaunchKernelGGL(k_w_final, dim3(F0), dim3(256), 0, st, f0_cl, f0_off, citem_first, citem_count,
+  hipLaunchKernelGGL(k_w_final, dim3(F0), dim3(256), 0, st, f0_cl, f0_off, k, citem_first, citem_count,
                      items, partial, W);
 }
 
@@ -447,7 +450,7 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
                                               const float* __restrict__ X, int d, int DM,
                                               const double* __restrict__ p_gid,
                                               const int32_t* __restrict__ s_off,
-                                              const int32_t* __restrict__ sp_off, int mode,
+                                              const int32_t* __restrict__ sp_off, int mode, int cap,
                                               int64_t* __restrict__ gid_view,
                                               int32_t* __restrict__ gid_pk, float* __restrict__ w32,
                                               float* __restrict__ aux32, float* __restrict__ Y32) {
@@ -457,6 +460,7 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
   const int j = slab[i];
   const int ps = pos[i];
   const int dst = sp_off[j] + (ps - s_off[j]);
+  if (dst >= cap || ps >= cap) return;  // capacity of the packed rows
   gid_view[ps] = g;
   gid_pk[dst] = g;
   w32[dst] = (float)(1.0 / p_gid[g]);
@@ -474,10 +478,10 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
 
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
                  const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
-                 const int32_t* s_off, const int32_t* sp_off, int mode, int64_t* gid_view,
+                 const int32_t* s_off, const int32_t* sp_off, int mode, int cap, int64_t* gid_view,
                  int32_t* gid_pk, float* w32, float* aux32, float* Y32) {
   hipLaunchKernelGGL(k_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos, n,
-                     X, d, DM, p_gid, s_off, sp_off, mode, gid_view, gid_pk, w32, aux32, Y32);
+                     X, d, DM, p_gid, s_off, sp_off, mode, cap, gid_view, gid_pk, w32, aux32, Y32);
 }
 
 // ----------------------------------------------------------------------------

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
                                                    void* __restrict__ Ym, float* __restrict__ bnorm) {
   using C = MCfg<P, DM>;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S_pad) return;
+  if (s >= S_pad || s >= sp_off[k]) return;  // sp_off[k]: packed rows in use
   // cluster of padded row s (binary search over sp_off)
   int lo = 0, hi = k;
   while (hi - lo > 1) {
@@ -433,6 +433,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     }
     pout[b] = P0 + 32 * b + prow;
     own[b] = labels[pout[b] < n ? pout[b] : n - 1];
+    own[b] = (unsigned)own[b] < (unsigned)k ? own[b] : 0;  // labels are checked before; stay in bounds
     w_own[b] = 0.0;
     bmin[b] = __builtin_inf();
   }

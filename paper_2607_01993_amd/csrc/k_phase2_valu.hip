@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
 #pragma unroll
     for (int c = 0; c < DM; ++c) x[c] *= rx;
   }
-  const int own = labels[er];
+  const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
 
   double w_own = 0.0;
   double bmin = __builtin_inf();
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kWave) void k_p2_valu_wide(
     ux = s2 > 0.f ? 0.f : 0.5f;
     for (int c = 0; c < kWideDM; ++c) xl[c * kWave] *= rx;
   }
-  const int own = labels[er];
+  const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
   double w_own = 0.0;
   double bmin = __builtin_inf();
   for (int j = 0; j < k; ++j) {

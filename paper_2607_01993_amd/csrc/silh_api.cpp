@@ -548,8 +548,8 @@ silh_status compact_and_pack(silh_ctx* c) {
   {
     Launch L(c, K_PACK);
     launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, c->d, c->DM, c->p_gid, c->s_off,
-                c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, c->gid_view, c->gid_pk, c->w32, c->aux32,
-                c->Y32);
+                c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, (int)c->S_pad, c->gid_view, c->gid_pk,
+                c->w32, c->aux32, c->Y32);
     CHK(L.done());
   }
   if (mfma_pack) {
@@ -646,8 +646,8 @@ silh_status phase1(silh_ctx* c) {
   if (pps && c->F0 > 0) {
     {
       Launch L(c, K_F0_PACK);
-      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, c->f0_gid, c->f0_cl,
-                     c->f0X);
+      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, (int)c->F0, c->f0_gid,
+                     c->f0_cl, c->f0X);
       CHK(L.done());
     }
     CHK(h2d(c, c->items, c->items_h));
@@ -661,7 +661,7 @@ silh_status phase1(silh_ctx* c) {
     }
     {
       Launch L(c, K_W_FINAL);
-      launch_w_final(c->st, c->f0_cl, (int)c->F0, c->f0_off, c->citem_first, c->citem_count, c->items,
+      launch_w_final(c->st, c->f0_cl, (int)c->F0, c->f0_off, k, c->citem_first, c->citem_count, c->items,
                      c->partial, c->W0);
       CHK(L.done());
     }
@@ -862,6 +862,7 @@ silh_status validate_params(const silh_params* prm, const float* X, const int32_
   return check_params(prm, X, labels, false, t);
 }
 int dm_for(int d) { return phase2_valu_dm(d); }
+silh_status set_error(silh_status st, const char* msg) { return fail(st, "%s", msg); }
 }  // namespace silh
 
 extern "C" {

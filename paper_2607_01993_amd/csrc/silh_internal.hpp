@@ -40,15 +40,17 @@ void launch_gather_at(hipStream_t st, const int32_t* scan, const int32_t* off, i
 // ---- Phase 1 -----------------------------------------------------------------
 void launch_f0_flag(hipStream_t st, const int32_t* perm, const int32_t* slab, int n,
                     const int32_t* csize, const double* q, int64_t t, uint64_t seed, int32_t* flag);
+// rows past `cap` (the capacity of f0_gid / f0_cl / f0X) are not written
 void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
-                    const int32_t* pos, int n, const float* X, int d, int DM, int64_t* f0_gid,
+                    const int32_t* pos, int n, const float* X, int d, int DM, int cap, int64_t* f0_gid,
                     int32_t* f0_cl, double* f0X);
 // one block per work item: item = (cluster, first sorted pos, end sorted pos,
 // first F0 index of the cluster, |F0_j|, base in `partial`)
 // f0X rows have stride DM (zero-padded)
 void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, int nitems,
                       const int32_t* perm, const float* X, int d, const double* f0X, double* partial);
-void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off,
+// F0 blocks at most; those at or past f0_off[k] return at once
+void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off, int k,
                     const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
                     const double* partial, double* W);
 void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t* perm,
@@ -57,10 +59,11 @@ void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t*
                  double* p_gid, int32_t* flag);
 void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, int32_t* flag);
 // Scatter the selected elements into the cluster-blocked, padded sample.
-// mode 0: raw coordinates; 1: rows scaled to unit L2 norm (cosine).
+// mode 0: raw coordinates; 1: rows scaled to unit L2 norm (cosine).  Rows at
+// or past `cap` (the capacity of the packed arrays) are not written.
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
                  const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
-                 const int32_t* s_off, const int32_t* sp_off, int mode, int64_t* gid_view,
+                 const int32_t* s_off, const int32_t* sp_off, int mode, int cap, int64_t* gid_view,
                  int32_t* gid_pk, float* w32, float* aux32, float* Y32);
 
 // ---- Phase 2 -----------------------------------------------------------------
@@ -98,6 +101,7 @@ int mfma_kp(int prec, int DM);   // contraction length of a packed row
 // mu: [k][KP] centres, zero beyond DM
 void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32_t* sp_off,
                    const int32_t* cnt, int k, float* mu);
+// packs rows [0, min(S_pad, sp_off[k]))
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
                       void* Ym, float* bnorm);
@@ -114,6 +118,30 @@ bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Ar
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
 
+// ---- device-side sizes for the capturable pipeline (k_graph.hip) ------------
+// bits of a clustering's status word
+constexpr int kStatusLabel = 1;    // a label outside [0, k) (set by k_unit_hist)
+constexpr int kStatusEmpty = 2;    // fewer than two nonempty clusters
+constexpr int kStatusF0 = 4;       // F0 larger than its capacity
+constexpr int kStatusPartial = 8;  // W(e_bar) partial sums larger than their capacity
+constexpr int kStatusSample = 16;  // padded sample larger than its capacity
+void launch_fill_i32(hipStream_t st, int32_t* p, int64_t count, int32_t v);
+// off[0..k] = exclusive prefix sums of csize; q[j] = min(1, (2/|C_j|) lnterm)
+void launch_index_sizes(hipStream_t st, const int32_t* csize, int k, double lnterm, int32_t* off, double* q,
+                        int* status);
+// clamps f0_off to f0_cap and writes the W work items (items_cap slots, the
+// unused ones empty), per-cluster first item / count and partial bases
+void launch_f0_items(hipStream_t st, const int32_t* csize, const int32_t* off, int32_t* f0_off, int k,
+                     int64_t t, int chunk, int f0_cap, int64_t part_cap, int items_cap, int32_t* citem_first,
+                     int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status);
+// cnt[j] = |F_j|, sp_off = offsets of the blocks padded to kSamplePad rows
+void launch_sample_sizes(hipStream_t st, const int32_t* s_off, int k, int s_cap, int32_t* cnt, int32_t* sp_off,
+                         int* status);
+// gid_pk = -1, w32 = aux32 = 0, Y32 = 0 over rows [0, min(*used, cap))
+void launch_clear_rows(hipStream_t st, const int32_t* used, int cap, int DM, int32_t* gid_pk, float* w32,
+                       float* aux32, float* Y32);
+void launch_put_status(hipStream_t st, const int* status, int32_t* out);
+
 // ---- host-side helpers shared by the C-ABI files ----------------------------
 }  // namespace silh
 #include "../../include/silh.h"
@@ -122,6 +150,8 @@ namespace silh {
 silh_status validate_params(const silh_params* prm, const float* X, const int32_t* labels, int64_t* t);
 // padded row width of the packed sample for dimension d (0 if unsupported)
 int dm_for(int d);
+// sets the thread's silh_last_error message and returns st
+silh_status set_error(silh_status st, const char* msg);
 
 // ---- cohesion / separation numerators from W_hat [n][k] ---------------------
 constexpr int kCohSepMaxBlocks = 1024;

@@ -103,6 +103,14 @@ SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                   ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int32)]),
+    "silh_graph_create": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "silh_graph_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "silh_graph_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "silh_graph_destroy": (None, [ctypes.c_void_p]),
     "silh_last_error": (ctypes.c_char_p, []),
     "silh_version": (ctypes.c_char_p, []),
 }
@@ -536,6 +544,67 @@ def silh_sweep(X, labels, ks, metric="eucl", prec="bf16", sampler="pps", t=128, 
                           K, int(m), int(workers), int(hbm_budget_bytes), sh, means, ctypes.byref(best)),
            "silh_sweep")
     return {"means": np.frombuffer(means, dtype=np.float64).copy(), "best": int(best.value)}
+
+
+class SilhGraphInfo(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int64), ("sample_cap", ctypes.c_int64), ("f0_cap", ctypes.c_int64),
+                ("bytes", ctypes.c_int64)]
+
+
+class SweepGraph:
+    """K clusterings of one dataset captured into one HIP graph
+    (include/silh_graph.h).  labels is a contiguous int32 [K, n] device tensor
+    whose contents are read at every run(), so new label sets may be written
+    into it between runs."""
+
+    def __init__(self, X, labels, ks, metric="eucl", prec="bf16", sampler="pps", t=128, delta=0.01, seed=0,
+                 chains=4, sample_cap=0.0, stream=None):
+        torch = _torch()
+        lib = load_library()
+        if labels.dtype != torch.int32 or labels.dim() != 2 or labels.shape[1] != X.shape[0] \
+                or not labels.is_contiguous() or not labels.is_cuda:
+            raise ValueError("labels must be a contiguous int32 [K, n] device tensor")
+        if X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous() or not X.is_cuda:
+            raise ValueError("X must be a contiguous float32 [n, d] device tensor")
+        self.K = labels.shape[0]
+        self.X, self.labels = X, labels  # referenced by the graph until close()
+        ksa = (ctypes.c_int32 * self.K)(*[int(v) for v in ks])
+        _, sh = _stream_handle(stream)
+        p = _params(X.shape[0], X.shape[1], 2, metric, prec, sampler, t, 0.0, delta, seed, use_torch_alloc=False)
+        out = ctypes.c_void_p()
+        _check(lib.silh_graph_create(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()),
+                                     ctypes.c_void_p(labels.data_ptr()), ksa, self.K, int(chains),
+                                     float(sample_cap), sh, ctypes.byref(out)), "silh_graph_create")
+        self.ptr = out
+
+    def run(self, stream=None):
+        import numpy as np
+        lib = load_library()
+        _, sh = _stream_handle(stream)
+        means = (ctypes.c_double * self.K)()
+        status = (ctypes.c_int32 * self.K)()
+        best, reruns = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.silh_graph_run(self.ptr, sh, means, status, ctypes.byref(best), ctypes.byref(reruns)),
+               "silh_graph_run")
+        return {"means": np.frombuffer(means, dtype=np.float64).copy(),
+                "status": [STATUS.get(int(v), int(v)) for v in status], "best": int(best.value),
+                "reruns": int(reruns.value)}
+
+    def info(self):
+        out = SilhGraphInfo()
+        _check(load_library().silh_graph_get_info(self.ptr, ctypes.byref(out)), "silh_graph_get_info")
+        return {f: int(getattr(out, f)) for f, _ in SilhGraphInfo._fields_}
+
+    def close(self):
+        if self.ptr:
+            load_library().silh_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -144,3 +144,22 @@ def test_server_layouts_and_argument_checks():
     lib.silh_server_destroy(None)
     t0 = lib.silh_server_now_ns()
     assert lib.silh_server_now_ns() >= t0 > 0
+
+
+def test_graph_layout_and_argument_checks():
+    assert ctypes.sizeof(native.SilhGraphInfo) == 32
+    lib = native.load_library()
+    out = ctypes.c_void_p()
+    p = native._params(1000, 8, 2, "eucl", "bf16", "pps", 32, 0.0, 0.01, 1, use_torch_alloc=False)
+    fake = ctypes.c_void_p(256)  # never dereferenced: every check below fails first
+    ks = (ctypes.c_int32 * 2)(3, 4)
+    assert lib.silh_graph_create(None, fake, fake, ks, 2, 2, 0.0, None, ctypes.byref(out)) == 1
+    assert lib.silh_graph_create(ctypes.byref(p), fake, fake, ks, 0, 2, 0.0, None, ctypes.byref(out)) == 1
+    for chains in (0, 17):
+        assert lib.silh_graph_create(ctypes.byref(p), fake, fake, ks, 2, chains, 0.0, None, ctypes.byref(out)) == 1
+    bad = (ctypes.c_int32 * 2)(3, 1)  # k = 1 for the second clustering
+    assert lib.silh_graph_create(ctypes.byref(p), fake, fake, bad, 2, 2, 0.0, None, ctypes.byref(out)) == 1
+    assert not out.value
+    assert lib.silh_graph_run(None, None, None, None, None, None) == 1
+    assert lib.silh_graph_get_info(None, None) == 1
+    lib.silh_graph_destroy(None)

@@ -1,0 +1,127 @@
+"""The k-sweep captured into one HIP graph (include/silh_graph.h): every
+clustering's mean equals the eager path's (silh_sample_init, silh_pps_sample,
+silh_scores) bit for bit, on the first launch and on replays with new labels,
+when a capacity overflows (the clustering is re-run eagerly), and next to
+clusterings with bad labels or a single nonempty cluster; and it matches the
+float64 oracle within the parity bars."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2607_01993_amd import native, synth
+from parity_util import LOWP_MEAN_ATOL, S_ATOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, d, ks, seed):
+    X = synth.exp_blobs(n, d, 6, seed=seed)
+    sets = [synth.voronoi_labels(X, synth.voronoi_centers(n, k, (seed, k))) for k in ks]
+    return X, sets
+
+
+def _eager(Xd, Ld, ks, metric, prec, sampler, t, seed):
+    out = []
+    for i, k in enumerate(ks):
+        ctx = native.silh_sample_init(Xd, Ld[i], k, metric, prec, sampler, t=t, seed=seed)
+        native.silh_pps_sample(ctx)
+        out.append(native.silh_scores(ctx, a=False, b=False, s=False)["mean"])
+        native.silh_destroy(ctx)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("metric,prec,sampler,d", [("eucl", "bf16", "pps", 16), ("eucl", "fp32", "pps", 16),
+                                                   ("cos", "fp32_valu", "pps", 16), ("canb", "fp32", "pps", 16),
+                                                   ("manh", "fp32", "uni", 16), ("cos", "fp8", "pps", 64),
+                                                   ("eucl", "bf16", "pps", 200), ("manh", "fp32", "pps", 200)])
+def test_graph_equals_eager(metric, prec, sampler, d):
+    n = 6000 if d <= 64 else 2500
+    ks = [2, 3, 4, 5, 7, 9]
+    print(f"graph metric={metric} prec={prec} sampler={sampler} n={n} d={d} K={len(ks)}", flush=True)
+    X, sets = _case(n, d, ks, seed=91)
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(np.stack(sets)).cuda().contiguous()
+    g = native.SweepGraph(Xd, Ld, ks, metric, prec, sampler, t=48, seed=7, chains=3)
+    info = g.info()
+    # 19 kernels per clustering without the initial sample (uniform sampler,
+    # vector-ALU Phase 2), 30 with it on the matrix cores
+    assert info["nodes"] >= len(ks) * 19
+    got = g.run()
+    g.close()
+    ref = _eager(Xd, Ld, ks, metric, prec, sampler, 48, 7)
+    assert got["status"] == ["SILH_OK"] * len(ks) and got["reruns"] == 0
+    assert np.array_equal(got["means"], ref), (got["means"], ref)
+    assert got["best"] == int(np.argmax(ref))
+
+
+def test_graph_matches_the_oracle():
+    ks = [2, 3, 5, 8]
+    X, sets = _case(4000, 8, ks, seed=92)
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(np.stack(sets)).cuda().contiguous()
+    g = native.SweepGraph(Xd, Ld, ks, "eucl", "fp32", t=40, seed=3, chains=2)
+    got = g.run()
+    g.close()
+    ref = oracle.sweep(X, sets, ks, "eucl", t=40, delta=0.01, seed=3, m=0)
+    assert np.max(np.abs(got["means"] - ref["means"])) <= S_ATOL, (got["means"], ref["means"])
+    g = native.SweepGraph(Xd, Ld, ks, "eucl", "bf16", t=40, seed=3, chains=2)
+    got = g.run()
+    g.close()
+    assert np.max(np.abs(got["means"] - ref["means"])) <= LOWP_MEAN_ATOL
+
+
+def test_graph_replay_reads_new_labels():
+    n, ks = 5000, [3, 4, 6]
+    X, sets_a = _case(n, 16, ks, seed=93)
+    sets_b = [synth.voronoi_labels(X, synth.voronoi_centers(n, k, (94, k))) for k in ks]
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(np.stack(sets_a)).cuda().contiguous()
+    g = native.SweepGraph(Xd, Ld, ks, "eucl", "bf16", t=32, seed=11, chains=2)
+    first = g.run()
+    Ld.copy_(torch.from_numpy(np.stack(sets_b)))
+    second = g.run()
+    third = g.run()
+    g.close()
+    ref_a = _eager(Xd, torch.from_numpy(np.stack(sets_a)).cuda(), ks, "eucl", "bf16", "pps", 32, 11)
+    ref_b = _eager(Xd, Ld, ks, "eucl", "bf16", "pps", 32, 11)
+    assert np.array_equal(first["means"], ref_a)
+    assert np.array_equal(second["means"], ref_b)
+    assert np.array_equal(third["means"], ref_b)
+
+
+def test_graph_capacity_overflow_reruns_eagerly():
+    ks = [2, 4, 6]
+    X, sets = _case(5000, 16, ks, seed=95)
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(np.stack(sets)).cuda().contiguous()
+    # a sample capacity of 0.05 k t rows (plus the padding) cannot hold a sample
+    g = native.SweepGraph(Xd, Ld, ks, "eucl", "bf16", t=64, seed=2, chains=2, sample_cap=0.05)
+    got = g.run()
+    g.close()
+    ref = _eager(Xd, Ld, ks, "eucl", "bf16", "pps", 64, 2)
+    assert got["reruns"] == len(ks)
+    assert got["status"] == ["SILH_OK"] * len(ks)
+    assert np.array_equal(got["means"], ref)
+
+
+def test_graph_bad_labels_and_single_cluster():
+    n, ks = 4000, [3, 4, 5, 3]
+    X, sets = _case(n, 8, ks, seed=96)
+    sets[1] = sets[1].copy()
+    sets[1][123] = 4          # outside [0, 4)
+    sets[2] = sets[2].copy()
+    sets[2][77] = -1
+    sets[3] = np.zeros(n, dtype=np.int32)  # one nonempty cluster of three
+    Xd = torch.from_numpy(X).cuda()
+    Ld = torch.from_numpy(np.stack(sets)).cuda().contiguous()
+    g = native.SweepGraph(Xd, Ld, ks, "eucl", "bf16", t=32, seed=5, chains=2)
+    got = g.run()
+    # the good clustering is unaffected by its neighbours, also on a replay
+    again = g.run()
+    g.close()
+    assert got["status"] == ["SILH_OK", "SILH_E_LABEL", "SILH_E_LABEL", "SILH_E_K"]
+    assert np.isnan(got["means"][1:]).all()
+    ref = _eager(Xd, Ld[:1], ks[:1], "eucl", "bf16", "pps", 32, 5)
+    assert got["means"][0] == ref[0] and again["means"][0] == ref[0]
+    assert got["best"] == 0
