@@ -35,6 +35,8 @@ namespace silh {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -369,15 +371,16 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   static_assert(C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
   constexpr float S2 = kFp8Scale * kFp8Scale;
   __shared__ double sh32[4 * PB];  // 32-element partials of the block, in element order
-  // long rows (HALF > 40): LDS tiles of 32 packed rows, rows padded by 16
-  // bytes so that the lanes' 16-byte reads fall in different banks
+  // long rows (bf16 / float32 with d >= 64, fp8 with d >= 128): LDS tiles of
+  // 32 packed rows shared by the block's waves, rows padded by 16 bytes so
+  // that the lanes' 16-byte reads fall in different banks
   constexpr int kRowB = C::KP * C::ELEM;
   constexpr int kLRow = kRowB + 16;
   constexpr int kTileB = 32 * kLRow;
   constexpr int kChRow = kRowB / 16;
   constexpr int kNCh = 32 * kChRow;
   constexpr int kPer = (kNCh + 255) / 256;
-  constexpr bool kLds = C::HALF > 40;
+  constexpr bool kLds = P == 2 ? C::HALF > 40 : C::HALF > 30;
   __shared__ __attribute__((aligned(16))) unsigned char ldsB[kLds ? 2 * kTileB : 16];
   __shared__ float ldsW[2][32];
   __shared__ int ldsG[2][32];
@@ -440,6 +443,18 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
 
   AFrag<P, DM> A[PB];
   float nxc[P == 2 ? PB : 1][16];   // fp8: 64^2 (alpha |x~_q|^2 + u_x) of the 16 C rows
+  // The packed cluster blocks are contiguous, so the tile after a cluster's
+  // last one is the first tile of the next cluster with samples: it is
+  // prefetched there, and a cluster normally starts with its first tile
+  // already loaded while its A operands are built.  Past the sample's end the
+  // last tile is re-read.  `pre` is the first row of the tile held in b0 (the
+  // register path) or in LDS buffer `cb` (the LDS path).
+  const int last_row = sp_off[k] - 32;
+  auto clamp_row = [&](int row) { return row <= last_row ? row : last_row; };
+  int pre = -1, cb = 0;
+  BFrag<P, DM> b0, b1;
+  float w0 = 0.f, w1 = 0.f;
+  int g0 = -1, g1 = -1;
   for (int j = 0; j < k; ++j) {
     // ---- A operands for cluster j: x~ = x - mu_j (mu zero-padded to KP),
     // rounded to the input precision, plus the augmentation
@@ -475,34 +490,44 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
                                      xq[32 * s + 4 * e + 3]);
         continue;
       }
+      if constexpr (P == 1) {
+        // bf16: each pair of centred coordinates is rounded into one packed
+        // register (the A fragment's layout) and its squares are added to
+        // the norm by one bf16 dot product (the products are exact in float32)
+        bf16x2 pk[C::HALF / 2];
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) {
-        float v = xr[b][i] - mv[i];
-        if (P == 1) v = q_bf16(v);
-        xq[i] = v;
-        part = fmaf(v, v, part);
-      }
-      const float nx = part + __shfl_xor(part, 32, kWave);
-      const float an = fmaf(alpha, nx, ux[b]);
-      float aug[C::AUG > 0 ? C::AUG : 1];
-      if constexpr (P == 0) {
-        aug[0] = an;
-        aug[1] = 1.0f;
-      } else if constexpr (P == 1) {
+        for (int i2 = 0; i2 < C::HALF / 2; ++i2) {
+          const f32x2 v = {xr[b][2 * i2] - mv[2 * i2], xr[b][2 * i2 + 1] - mv[2 * i2 + 1]};
+          pk[i2] = __builtin_convertvector(v, bf16x2);
+          part = __builtin_amdgcn_fdot2_f32_bf16(pk[i2], pk[i2], part, false);
+        }
+        const float an = fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
+        float aug[6];
         split3(an, aug[0], aug[1], aug[2]);
         aug[3] = aug[4] = aug[5] = 1.0f;
-      }
+        // the augmentation columns hold zeros in the upper half's pairs
 #pragma unroll
-      for (int q = 0; q < C::AUG; ++q) xq[AUG0 + q] = h ? aug[q] : xq[AUG0 + q];
-      if constexpr (P == 0) {
-#pragma unroll
-        for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
-      } else if constexpr (P == 1) {
+        for (int q = 0; q < C::AUG; q += 2)
+          pk[(AUG0 + q) / 2] = h ? __builtin_convertvector((f32x2{aug[q], aug[q + 1]}), bf16x2) : pk[(AUG0 + q) / 2];
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) A[b].v[s][e] = (__bf16)xq[8 * s + e];
+          for (int e = 0; e < 8; ++e) A[b].v[s][e] = pk[4 * s + e / 2][e % 2];
+        continue;
       }
+#pragma unroll
+      for (int i = 0; i < C::HALF; ++i) {
+        const float v = xr[b][i] - mv[i];
+        xq[i] = v;
+        part = fmaf(v, v, part);
+      }
+      // float32: the norm and a 1 ride along as two extra columns
+      const float nx = part + __shfl_xor(part, 32, kWave);
+      const float an = fmaf(alpha, nx, ux[b]);
+      xq[AUG0] = h ? an : xq[AUG0];
+      xq[AUG0 + 1] = h ? 1.0f : xq[AUG0 + 1];
+#pragma unroll
+      for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
     }
 
     // ---- sweep the cluster's sample tiles (B operand double-buffered: the
@@ -583,7 +608,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         g = 0;
       }
     };
-    if constexpr (C::HALF > 40) {
+    if constexpr (kLds) {
       // Long rows: the block's four waves sweep the same tiles, so each tile
       // is loaded once per block into LDS (double-buffered: tile t + 1 is
       // fetched into registers while tile t is computed, then stored to the
@@ -614,14 +639,16 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
           ldsG[buf][threadIdx.x] = sg;
         }
       };
-      if (ntile > 0) {
+      if (ntile > 0 && pre != base) {  // block-uniform: every wave sweeps the same clusters
         fetch(base);
-        store(0);
+        store(cb);
+        pre = base;
+        __syncthreads();
       }
-      __syncthreads();
       for (int t = 0; t < ntile; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < ntile) fetch(base + (t + 1) * 32);
+        const int buf = cb;
+        const int nrow = clamp_row(base + (t + 1) * 32);
+        fetch(nrow);
         const unsigned char* tl = ldsB + buf * kTileB + col * kLRow + h * C::HALF * C::ELEM;
         auto fromLds = [&](int q) {
           if constexpr (P == 0) {
@@ -634,27 +661,30 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
           }
         };
         tile(fromLds, ldsW[buf][col], ldsG[buf][col], t + 1 == ntile);
-        if (t + 1 < ntile) store(buf ^ 1);
+        store(buf ^ 1);
         __syncthreads();
+        cb = buf ^ 1;
+        pre = nrow;
       }
     } else {
-      // Tiles go in pairs with unconditional prefetches (the one past the
-      // cluster's last tile re-reads that tile), so the wait before each
-      // tile covers only that tile's loads; an odd last tile runs after the
-      // loop from the buffer already loaded.
-      BFrag<P, DM> b0, b1;
-      float w0 = 0.f, w1 = 0.f;
-      int g0 = -1, g1 = -1;
-      if (ntile > 0) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
+      // Tiles go in pairs with unconditional prefetches, so the wait before
+      // each tile covers only that tile's loads; an odd last tile runs after
+      // the loop from the buffer already loaded, and its successor is loaded
+      // into the same buffer once its MFMAs are issued.
+      if (ntile > 0 && pre != base) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
       int t = 0;
       for (; t + 2 <= ntile; t += 2) {
         load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
         tile([&](int q) { return b0.v[q]; }, w0, g0, false);
-        const int t2 = t + 2 < ntile ? t + 2 : ntile - 1;
-        load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + t2 * 32, lane_off, col, b0, w0, g0);
+        pre = clamp_row(base + (t + 2) * 32);
+        load_tile<P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
         tile([&](int q) { return b1.v[q]; }, w1, g1, t + 2 == ntile);
       }
-      if (t < ntile) tile([&](int q) { return b0.v[q]; }, w0, g0, true);
+      if (t < ntile) {
+        tile([&](int q) { return b0.v[q]; }, w0, g0, true);
+        pre = clamp_row(base + ntile * 32);
+        load_tile<P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
+      }
     }
     const int sz = csize[j];
 #pragma unroll
