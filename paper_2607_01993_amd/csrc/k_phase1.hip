@@ -169,15 +169,38 @@ void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, co
 // a fixed-order block reduction).
 // item layout: [cluster, begin, end, f0_begin, f0_count, partial_base]
 // ----------------------------------------------------------------------------
+// kEB float64 values per lane summed over the wave: two exchange steps (lane
+// distance 32, then 16) leave each lane one of the four values, then a
+// butterfly over distances 8, 4, 2, 1.  Every sum pairs the same lanes in the
+// same order as a plain butterfly over 32..1 (a + b == b + a), so each total
+// equals that butterfly's bit for bit.  Lanes with (lane & 15) == 0 end up
+// holding the total of value 2 * ((lane >> 5) & 1) + ((lane >> 4) & 1).
+__device__ __forceinline__ double wave_sum4_f64(const double (&v)[kEB], int lane) {
+  static_assert(kEB == 4, "four values per exchange");
+  const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1;
+  const double r0 = __shfl_xor(b5 ? v[0] : v[2], 32, kWave);
+  const double r1 = __shfl_xor(b5 ? v[1] : v[3], 32, kWave);
+  const double u0 = (b5 ? v[2] : v[0]) + r0;
+  const double u1 = (b5 ? v[3] : v[1]) + r1;
+  const double r = __shfl_xor(b4 ? u0 : u1, 16, kWave);
+  double w = (b4 ? u1 : u0) + r;
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) w += __shfl_xor(w, o, kWave);
+  return w;
+}
+
+constexpr int kWSlots = 64;  // partial sums gathered in LDS between two barriers
+
 template <int M, int DM>
 __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ items,
                                                    const int32_t* __restrict__ perm,
                                                    const float* __restrict__ X, int d,
                                                    const double* __restrict__ f0X,
                                                    double* __restrict__ partial) {
-  __shared__ double sh[4];
+  __shared__ double sh[4][kWSlots];  // per wave, per initial element of the current batch
   const int32_t* it = items + (size_t)blockIdx.x * 6;
   const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   // one member row per thread (items hold at most 256 members), read once
   const int r = begin + threadIdx.x;
   const bool have = r < end;
@@ -189,17 +212,47 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
 #pragma unroll
     for (int c = 0; c < DM; ++c) x[c] = 0.0f;
   }
-  for (int e0 = 0; e0 < f0n; e0 += kEB) {
-    const int ne = f0n - e0 < kEB ? f0n - e0 : kEB;
+  if constexpr (DM > 64) {
+    // long rows: one block sum per initial element (the batched form below
+    // does not fit the registers next to a 128-float row)
+    for (int e0 = 0; e0 < f0n; e0 += kEB) {
+      const int ne = f0n - e0 < kEB ? f0n - e0 : kEB;
 #pragma unroll
-    for (int e = 0; e < kEB; ++e) {
-      const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
-      const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
-      if (e < ne) {  // ne is uniform over the block
-        const double tot = block_sum_f64<256>(have ? dv : 0.0, sh);
-        if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
+      for (int e = 0; e < kEB; ++e) {
+        const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
+        const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
+        if (e < ne) {  // ne is uniform over the block
+          const double tot = block_sum_f64<256>(have ? dv : 0.0, &sh[0][0]);
+          if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
+        }
       }
     }
+    return;
+  }
+  // per initial element: member distances summed over the wave, then the
+  // four wave sums in wave order (one thread per element)
+  for (int s0 = 0; s0 < f0n; s0 += kWSlots) {
+    const int ns = f0n - s0 < kWSlots ? f0n - s0 : kWSlots;
+    for (int e0 = 0; e0 < ns; e0 += kEB) {
+      double dv[kEB];
+#pragma unroll
+      for (int e = 0; e < kEB; ++e) {
+        const int ee = e0 + e < ns ? e0 + e : ns - 1;   // repeats a row instead of branching
+        const double v = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + s0 + ee) * DM);
+        dv[e] = have ? v : 0.0;
+      }
+      const double w = wave_sum4_f64(dv, lane);
+      const int slot = e0 + 2 * ((lane >> 5) & 1) + ((lane >> 4) & 1);
+      if ((lane & 15) == 0 && slot < ns) sh[wid][slot] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < ns) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t += sh[i][threadIdx.x];
+      partial[pb + s0 + threadIdx.x] = t;
+    }
+    __syncthreads();
   }
 }
 

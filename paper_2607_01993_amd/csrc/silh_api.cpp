@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <array>
 #include <atomic>
 #include <initializer_list>
@@ -111,7 +112,10 @@ struct silh_ctx {
   int64_t S = 0, S_pad = 0, F0 = 0;
   int32_t *flag = nullptr, *pos = nullptr, *scan_tmp = nullptr;
   int32_t *f0_off = nullptr, *f0_cl = nullptr, *items = nullptr, *citem_first = nullptr,
-          *citem_count = nullptr;
+          *citem_count = nullptr, *imeta = nullptr;
+  int64_t* ibase = nullptr;
+  int* p1_status = nullptr;  // capacity bits of the device-built W work items
+  int p1_status_h = 0;
   int64_t *f0_gid = nullptr, *gid_view = nullptr;
   double *f0X = nullptr, *W0 = nullptr, *partial = nullptr, *p_gid = nullptr;
   int32_t *s_off = nullptr, *sp_off = nullptr, *cnt = nullptr, *gid_pk = nullptr;
@@ -504,7 +508,11 @@ silh_status create(const silh_params* prm, const float* X, const int32_t* labels
 
 // Scan the selection flags, read the per-cluster sample counts back, and pack
 // the selected rows into the padded cluster-blocked layout.
-silh_status compact_and_pack(silh_ctx* c) {
+// With *overflow non-null, Phase 1 built its W work items on the device: the
+// F0 offsets and the capacity status come back with the sample offsets (one
+// read-back), and *overflow reports whether a capacity was exceeded (then
+// nothing is packed and the caller runs Phase 1 again with exact sizes).
+silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
   const int n = c->n, k = c->k;
   {
     Launch L(c, K_SCAN);
@@ -514,7 +522,17 @@ silh_status compact_and_pack(silh_ctx* c) {
   launch_gather_at(c->st, c->pos, c->off, k, c->s_off);
   HIPCHK(hipGetLastError());
   c->s_off32_h.assign(k + 1, 0);
-  CHK(fetch(c, {{c->s_off32_h.data(), c->s_off, (k + 1) * sizeof(int32_t)}}));
+  if (overflow) {
+    CHK(fetch(c, {{c->s_off32_h.data(), c->s_off, (k + 1) * sizeof(int32_t)},
+                  {c->f0_off32_h.data(), c->f0_off, (k + 1) * sizeof(int32_t)},
+                  {&c->p1_status_h, c->p1_status, sizeof(int)}}));
+    *overflow = (c->p1_status_h & (kStatusF0 | kStatusPartial)) != 0;
+    if (*overflow) return SILH_OK;
+    for (int j = 0; j <= k; ++j) c->f0_off_h[j] = c->f0_off32_h[j];
+    c->F0 = c->f0_off_h[k];
+  } else {
+    CHK(fetch(c, {{c->s_off32_h.data(), c->s_off, (k + 1) * sizeof(int32_t)}}));
+  }
   c->s_off_h.assign(k + 1, 0);
   c->cnt_h.assign(k, 0);
   c->sp_off_h.assign(k + 1, 0);
@@ -574,7 +592,9 @@ silh_status sample_stage_buffers(silh_ctx* c) {
   free_list(c, c->alloc_sample);
   c->state = 0;
   c->f0_gid = c->gid_view = nullptr;
-  c->f0_cl = c->items = c->citem_first = c->citem_count = c->gid_pk = nullptr;
+  c->f0_cl = c->items = c->citem_first = c->citem_count = c->gid_pk = c->imeta = nullptr;
+  c->ibase = nullptr;
+  c->p1_status = nullptr;
   c->f0X = c->W0 = c->partial = nullptr;
   c->w32 = c->aux32 = c->Y32 = c->mu = c->bnorm = nullptr;
   c->Ym = nullptr;
@@ -587,13 +607,20 @@ silh_status sample_stage_buffers(silh_ctx* c) {
   return cv.commit(c, c->alloc_sample);
 }
 
-silh_status phase1(silh_ctx* c) {
+// Phase 1.  PPS builds the W(e_bar) work items on the device from the F0
+// offsets (k_f0_items) with the F0 arrays at a capacity of 64k + 1024 rows,
+// so nothing is read back between the initial sample and the draw; if F0 (or
+// the partial sums) outgrow their capacity, Phase 1 runs again with the F0
+// offsets read back and the items built on the host (host_items).
+silh_status phase1(silh_ctx* c, bool host_items = false) {
   const int n = c->n, k = c->k, d = c->d;
   CHK(sample_stage_buffers(c));
   c->F0 = 0;
   c->f0_off_h.assign(k + 1, 0);
   c->f0_off32_h.assign(k + 1, 0);
   const bool pps = c->prm.sampler == SILH_PPS;
+  // members per work item: one per thread of the W-pass block
+  const int chunk = c->DM > 128 ? kWChunkWide : kWChunk;
   if (pps) {
     // initial sample F^0
     {
@@ -608,60 +635,88 @@ silh_status phase1(silh_ctx* c) {
     }
     launch_gather_at(c->st, c->pos, c->off, k, c->f0_off);
     HIPCHK(hipGetLastError());
-    CHK(fetch(c, {{c->f0_off32_h.data(), c->f0_off, (k + 1) * sizeof(int32_t)}}));
-    for (int j = 0; j <= k; ++j) c->f0_off_h[j] = c->f0_off32_h[j];
-    c->F0 = c->f0_off_h[k];
   } else {
     HIPCHK(hipMemsetAsync(c->f0_off, 0, (size_t)(k + 1) * sizeof(int32_t), c->st));
   }
-  // work items for W(e_bar)
-  c->items_h.clear();
-  c->citem_first_h.assign(k, 0);
-  c->citem_count_h.assign(k, 0);
-  int64_t pbase = 0;
-  // members per work item: one per thread of the W-pass block
-  const int chunk = c->DM > 128 ? kWChunkWide : kWChunk;
-  if (pps && c->F0 > 0) {
-    for (int j = 0; j < k; ++j) {
-      const int fj = c->f0_off32_h[j + 1] - c->f0_off32_h[j];
-      c->citem_first_h[j] = (int32_t)(c->items_h.size() / 6);
-      if ((int64_t)c->csize_h[j] <= c->t || fj == 0) continue;
-      for (int b = c->off_h[j]; b < c->off_h[j + 1]; b += chunk) {
-        const int e = b + chunk < c->off_h[j + 1] ? b + chunk : c->off_h[j + 1];
-        c->items_h.insert(c->items_h.end(), {j, b, e, c->f0_off32_h[j], fj, (int32_t)pbase});
-        pbase += fj;
-        c->citem_count_h[j] += 1;
-      }
-      if (pbase > (int64_t)1 << 30) return fail(SILH_E_ARG, "initial sample too large");
+  int nitems = 0;
+  int64_t f0_rows = 0;
+  if (pps && !host_items) {
+    const int64_t f0_cap = std::min<int64_t>(n, 64 * (int64_t)k + 1024);
+    const int64_t items_cap = ceil_div(n, chunk) + k;
+    const int64_t part_cap = std::min<int64_t>((int64_t)1 << 30, items_cap * 64);
+    {
+      Carve cv;
+      cv.add(&c->f0_gid, (size_t)f0_cap).add(&c->f0_cl, (size_t)f0_cap).add(&c->f0X, (size_t)f0_cap * c->DM);
+      cv.add(&c->W0, (size_t)f0_cap).add(&c->items, (size_t)items_cap * 6).add(&c->citem_first, (size_t)k);
+      cv.add(&c->citem_count, (size_t)k).add(&c->partial, (size_t)part_cap).add(&c->ibase, (size_t)k);
+      cv.add(&c->imeta, 1).add(&c->p1_status, 1);
+      CHK(cv.commit(c, c->alloc_sample));
     }
-  }
-  const int nitems = (int)(c->items_h.size() / 6);
-  {
-    Carve cv;
-    cv.add(&c->f0_gid, (size_t)c->F0).add(&c->f0_cl, (size_t)c->F0).add(&c->f0X, (size_t)c->F0 * c->DM);
-    cv.add(&c->W0, (size_t)c->F0).add(&c->items, c->items_h.size()).add(&c->citem_first, (size_t)k);
-    cv.add(&c->citem_count, (size_t)k).add(&c->partial, (size_t)pbase);
-    CHK(cv.commit(c, c->alloc_sample));
-  }
-  if (pps && c->F0 > 0) {
+    HIPCHK(hipMemsetAsync(c->p1_status, 0, sizeof(int), c->st));
+    launch_f0_items(c->st, c->csize, c->off, c->f0_off, k, c->t, chunk, (int)f0_cap, part_cap, (int)items_cap,
+                    c->citem_first, c->citem_count, c->ibase, c->imeta, c->items, c->p1_status);
+    HIPCHK(hipGetLastError());
     {
       Launch L(c, K_F0_PACK);
-      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, (int)c->F0, c->f0_gid,
+      launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, (int)f0_cap, c->f0_gid,
                      c->f0_cl, c->f0X);
       CHK(L.done());
     }
-    CHK(h2d(c, c->items, c->items_h));
-    CHK(h2d(c, c->citem_first, c->citem_first_h));
-    CHK(h2d(c, c->citem_count, c->citem_count_h));
+    nitems = (int)items_cap;  // the unused item slots are empty
+    f0_rows = f0_cap;         // W blocks past F0 return at once
+  } else if (pps) {
+    CHK(fetch(c, {{c->f0_off32_h.data(), c->f0_off, (k + 1) * sizeof(int32_t)}}));
+    for (int j = 0; j <= k; ++j) c->f0_off_h[j] = c->f0_off32_h[j];
+    c->F0 = c->f0_off_h[k];
+    // work items for W(e_bar), built on the host
+    c->items_h.clear();
+    c->citem_first_h.assign(k, 0);
+    c->citem_count_h.assign(k, 0);
+    int64_t pbase = 0;
+    if (c->F0 > 0) {
+      for (int j = 0; j < k; ++j) {
+        const int fj = c->f0_off32_h[j + 1] - c->f0_off32_h[j];
+        c->citem_first_h[j] = (int32_t)(c->items_h.size() / 6);
+        if ((int64_t)c->csize_h[j] <= c->t || fj == 0) continue;
+        for (int b = c->off_h[j]; b < c->off_h[j + 1]; b += chunk) {
+          const int e = b + chunk < c->off_h[j + 1] ? b + chunk : c->off_h[j + 1];
+          c->items_h.insert(c->items_h.end(), {j, b, e, c->f0_off32_h[j], fj, (int32_t)pbase});
+          pbase += fj;
+          c->citem_count_h[j] += 1;
+        }
+        if (pbase > (int64_t)1 << 30) return fail(SILH_E_ARG, "initial sample too large");
+      }
+    }
+    nitems = (int)(c->items_h.size() / 6);
+    f0_rows = c->F0;
+    {
+      Carve cv;
+      cv.add(&c->f0_gid, (size_t)c->F0).add(&c->f0_cl, (size_t)c->F0).add(&c->f0X, (size_t)c->F0 * c->DM);
+      cv.add(&c->W0, (size_t)c->F0).add(&c->items, c->items_h.size()).add(&c->citem_first, (size_t)k);
+      cv.add(&c->citem_count, (size_t)k).add(&c->partial, (size_t)pbase);
+      CHK(cv.commit(c, c->alloc_sample));
+    }
+    if (c->F0 > 0) {
+      {
+        Launch L(c, K_F0_PACK);
+        launch_f0_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, d, c->DM, (int)c->F0, c->f0_gid,
+                       c->f0_cl, c->f0X);
+        CHK(L.done());
+      }
+      CHK(h2d(c, c->items, c->items_h));
+      CHK(h2d(c, c->citem_first, c->citem_first_h));
+      CHK(h2d(c, c->citem_count, c->citem_count_h));
+    }
+  }
+  if (pps && nitems > 0 && f0_rows > 0) {
     {
       Launch L(c, K_W_PARTIAL);
-      launch_w_partial(c->st, c->prm.metric, c->DM, c->items, nitems, c->perm, c->X, d, c->f0X,
-                       c->partial);
+      launch_w_partial(c->st, c->prm.metric, c->DM, c->items, nitems, c->perm, c->X, d, c->f0X, c->partial);
       CHK(L.done());
     }
     {
       Launch L(c, K_W_FINAL);
-      launch_w_final(c->st, c->f0_cl, (int)c->F0, c->f0_off, k, c->citem_first, c->citem_count, c->items,
+      launch_w_final(c->st, c->f0_cl, (int)f0_rows, c->f0_off, k, c->citem_first, c->citem_count, c->items,
                      c->partial, c->W0);
       CHK(L.done());
     }
@@ -672,7 +727,13 @@ silh_status phase1(silh_ctx* c) {
                 c->prm.seed, c->f0_off, c->f0X, c->W0, c->p_gid, c->flag);
     CHK(L.done());
   }
-  return compact_and_pack(c);
+  if (pps && !host_items) {
+    bool overflow = false;
+    CHK(compact_and_pack(c, &overflow));
+    if (overflow) return phase1(c, true);
+    return SILH_OK;
+  }
+  return compact_and_pack(c, nullptr);
 }
 
 // ---- autotuning of the MFMA Phase-2 block shape ------------------------------
@@ -910,7 +971,7 @@ silh_status silh_exact(const silh_params* prm, const float* X, const int32_t* la
     launch_fill_all(c->st, c->perm, c->n, c->p_gid, c->flag);
     st = L.done();
   }
-  if (st == SILH_OK) st = compact_and_pack(c);
+  if (st == SILH_OK) st = compact_and_pack(c, nullptr);
   if (st == SILH_OK) st = run_phase2(c, a, b, s, nullptr, s_mean_host);
   std::string msg = g_err;
   silh_destroy(c);
@@ -955,7 +1016,7 @@ silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_
     launch_fill_all(c->st, c->perm, c->n, c->p_gid, c->flag);
     st = L.done();
   }
-  if (st == SILH_OK) st = compact_and_pack(c);
+  if (st == SILH_OK) st = compact_and_pack(c, nullptr);
   if (st == SILH_OK) st = rows_phase2(c, rows, m, a, b, s, s_mean_host);
   std::string msg = g_err;
   silh_destroy(c);
