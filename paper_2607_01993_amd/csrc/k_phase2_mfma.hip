@@ -105,8 +105,10 @@ __global__ __launch_bounds__(256) void k_center(const float* __restrict__ Y32, i
   for (int c0 = 0; c0 < KP; c0 += 32) {
     const int c = c0 + cc;
     double s = 0.0;
-    if (c < DM)
-      for (int r = rg; r < m; r += 8) s += (double)Y32[(size_t)(base + r) * DM + c];
+    if (c < DM) {
+#pragma unroll 8
+      for (int r = rg; r < m; r += 8) s += (double)Y32[(size_t)(base + r) * DM + c];  // loads issued ahead
+    }
     part[threadIdx.x] = s;
     __syncthreads();
     if (rg == 0 && c < KP) {

@@ -286,7 +286,8 @@ __global__ __launch_bounds__(256) void k_mean(const double* __restrict__ bpart, 
                                               double* __restrict__ out) {
   __shared__ double ss[256], cc[256];
   double s = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) neumaier_add(s, c, bpart[i]);
+#pragma unroll 8
+  for (int i = threadIdx.x; i < nb; i += 256) neumaier_add(s, c, bpart[i]);  // loads issued ahead
   ss[threadIdx.x] = s;
   cc[threadIdx.x] = c;
   __syncthreads();
