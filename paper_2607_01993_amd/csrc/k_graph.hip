@@ -95,14 +95,17 @@ void launch_index_sizes(hipStream_t st, const int32_t* csize, int k, double lnte
 // clamped to f0_cap (kStatusF0 when it did not fit); a partial-sum total past
 // part_cap sets kStatusPartial and leaves every cluster without items.
 // Writes citem_first / citem_count / ibase (first item, count, partial base
-// per cluster) and meta[0] = item count.
+// per cluster) and meta[0] = item count; with dbase, the per-cluster bases of
+// the kept member distances (|C_j| |F0_j| each, same clusters) and meta[1] = 1
+// when their total fits dist_cap.
 __global__ __launch_bounds__(1024) void k_f0_items(const int32_t* __restrict__ csize,
                                                    int32_t* __restrict__ f0_off, int k, int64_t t, int chunk,
                                                    int f0_cap, int64_t part_cap,
                                                    int32_t* __restrict__ citem_first,
                                                    int32_t* __restrict__ citem_count,
                                                    int64_t* __restrict__ ibase, int32_t* __restrict__ meta,
-                                                   int* __restrict__ status) {
+                                                   int* __restrict__ status, int64_t* __restrict__ dbase,
+                                                   int64_t dist_cap) {
   __shared__ int64_t part[1024];
   __shared__ int over;
   if (threadIdx.x == 0) over = f0_off[k] > f0_cap;
@@ -112,27 +115,34 @@ __global__ __launch_bounds__(1024) void k_f0_items(const int32_t* __restrict__ c
   const int per = (k + 1023) / 1024;
   const int j0 = threadIdx.x * per;
   const int j1 = j0 + per < k ? j0 + per : k;
-  int64_t ni = 0, np = 0;
+  int64_t ni = 0, np = 0, nd = 0;
   for (int j = j0; j < j1; ++j) {
     const int fj = f0_off[j + 1] - f0_off[j];
-    const int64_t items = ((int64_t)csize[j] > t && fj > 0) ? ((int64_t)csize[j] + chunk - 1) / chunk : 0;
+    const bool on = (int64_t)csize[j] > t && fj > 0;
+    const int64_t items = on ? ((int64_t)csize[j] + chunk - 1) / chunk : 0;
     ni += items;
     np += items * fj;
+    nd += on ? (int64_t)csize[j] * fj : 0;
   }
-  int64_t ni_tot = 0, np_tot = 0;
+  int64_t ni_tot = 0, np_tot = 0, nd_tot = 0;
   int64_t irun = block_scan_excl_1024(ni, part, &ni_tot);
   int64_t prun = block_scan_excl_1024(np, part, &np_tot);
+  int64_t drun = block_scan_excl_1024(nd, part, &nd_tot);
   const bool drop = np_tot > part_cap;
   for (int j = j0; j < j1; ++j) {
     const int fj = f0_off[j + 1] - f0_off[j];
-    const int64_t items = ((int64_t)csize[j] > t && fj > 0 && !drop) ? ((int64_t)csize[j] + chunk - 1) / chunk : 0;
+    const bool on = (int64_t)csize[j] > t && fj > 0;
+    const int64_t items = (on && !drop) ? ((int64_t)csize[j] + chunk - 1) / chunk : 0;
     citem_first[j] = drop ? 0 : (int32_t)irun;
     citem_count[j] = (int32_t)items;
     ibase[j] = prun;
+    if (dbase) dbase[j] = drun;
     irun += items;
     prun += items * fj;
+    drun += on ? (int64_t)csize[j] * fj : 0;
   }
   if (threadIdx.x == 0) {
+    meta[1] = (dbase != nullptr && !drop && nd_tot <= dist_cap) ? 1 : 0;
     meta[0] = drop ? 0 : (int32_t)ni_tot;
     if (over) *status |= kStatusF0;
     if (drop) *status |= kStatusPartial;
@@ -184,9 +194,10 @@ __global__ __launch_bounds__(256) void k_items_fill(const int32_t* __restrict__ 
 
 void launch_f0_items(hipStream_t st, const int32_t* csize, const int32_t* off, int32_t* f0_off, int k,
                      int64_t t, int chunk, int f0_cap, int64_t part_cap, int items_cap, int32_t* citem_first,
-                     int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status) {
+                     int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status,
+                     int64_t* dbase, int64_t dist_cap) {
   hipLaunchKernelGGL(k_f0_items, dim3(1), dim3(1024), 0, st, csize, f0_off, k, t, chunk, f0_cap, part_cap,
-                     citem_first, citem_count, ibase, meta, status);
+                     citem_first, citem_count, ibase, meta, status, dbase, dist_cap);
   hipLaunchKernelGGL(k_items_fill, dim3((int)ceil_div(items_cap, 256)), dim3(256), 0, st, off, f0_off,
                      citem_first, ibase, meta, k, chunk, items_cap, items);
 }
@@ -246,6 +257,12 @@ void launch_clear_rows(hipStream_t st, const int32_t* used, int cap, int DM, int
 }
 
 __global__ void k_put_status(const int* __restrict__ status, int32_t* __restrict__ out) { *out = *status; }
+
+int64_t dist_capacity(int64_t n, double lnterm) {
+  const double v = (double)n * (2.5 * lnterm + 8.0);
+  const double cap = (double)((int64_t)1 << 27);
+  return (int64_t)(v < cap ? v : cap);
+}
 
 void launch_put_status(hipStream_t st, const int* status, int32_t* out) {
   hipLaunchKernelGGL(k_put_status, dim3(1), dim3(1), 0, st, status, out);

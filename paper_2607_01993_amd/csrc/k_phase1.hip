@@ -196,10 +196,19 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
                                                    const int32_t* __restrict__ perm,
                                                    const float* __restrict__ X, int d,
                                                    const double* __restrict__ f0X,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, DistStore ds) {
   __shared__ double sh[4][kWSlots];  // per wave, per initial element of the current batch
   const int32_t* it = items + (size_t)blockIdx.x * 6;
   const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
+  // the kept distances of this item's members (cluster it[0]): one column
+  // per initial element, members contiguous
+  double* keep = nullptr;
+  int64_t kstride = 0;
+  if (ds.d != nullptr && f0n > 0 && *ds.use) {
+    const int j = it[0];
+    kstride = ds.off[j + 1] - ds.off[j];
+    keep = ds.d + ds.base[j] + (begin - ds.off[j]) + threadIdx.x;
+  }
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   // one member row per thread (items hold at most 256 members), read once
   const int r = begin + threadIdx.x;
@@ -222,6 +231,7 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
         const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
         const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
         if (e < ne) {  // ne is uniform over the block
+          if (keep != nullptr && have) keep[(int64_t)(e0 + e) * kstride] = dv;
           const double tot = block_sum_f64<256>(have ? dv : 0.0, &sh[0][0]);
           if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
         }
@@ -240,6 +250,7 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
         const int ee = e0 + e < ns ? e0 + e : ns - 1;   // repeats a row instead of branching
         const double v = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + s0 + ee) * DM);
         dv[e] = have ? v : 0.0;
+        if (keep != nullptr && have && e0 + e < ns) keep[(int64_t)(s0 + e0 + e) * kstride] = v;
       }
       const double w = wave_sum4_f64(dv, lane);
       const int slot = e0 + 2 * ((lane >> 5) & 1) + ((lane >> 4) & 1);
@@ -310,7 +321,8 @@ __global__ __launch_bounds__(kWave) void k_w_partial_wide(const int32_t* __restr
   } while (0)
 
 void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, int nitems,
-                      const int32_t* perm, const float* X, int d, const double* f0X, double* partial) {
+                      const int32_t* perm, const float* X, int d, const double* f0X, double* partial,
+                      DistStore ds) {
   if (nitems <= 0) return;
   if (DM == kWideDM) {
 #define SILH_WP(MM) hipLaunchKernelGGL(k_w_partial_wide<MM>, dim3(nitems), dim3(kWave), 0, st, items, perm, X, d, f0X, partial)
@@ -323,7 +335,7 @@ void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, 
 #undef SILH_WP
     return;
   }
-  SILH_P1_DISPATCH(k_w_partial, dim3(nitems), items, perm, X, d, f0X, partial);
+  SILH_P1_DISPATCH(k_w_partial, dim3(nitems), items, perm, X, d, f0X, partial, ds);
 }
 
 // W(e_bar): sum of its cluster's item partials.  One block per initial
@@ -368,7 +380,8 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
                                               uint64_t seed, const int32_t* __restrict__ f0_off,
                                               const double* __restrict__ f0X,
                                               const double* __restrict__ W,
-                                              double* __restrict__ p_gid, int32_t* __restrict__ flag) {
+                                              double* __restrict__ p_gid, int32_t* __restrict__ flag,
+                                              DistStore ds) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int g = perm[i];
@@ -383,6 +396,26 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
     p = (double)t / (double)m;
     p = p < 1.0 ? p : 1.0;
     sel = uniform53(seed, (uint64_t)g, kStreamUNI) < p ? 1 : 0;
+  } else if (ds.d != nullptr && *ds.use && i >= ds.off[j] && i < ds.off[j + 1]) {
+    // the W pass kept d(e, e_bar) for every initial element of the cluster
+    // (the same float64 values the branch below evaluates); a position
+    // outside its cluster's range (only where a label was out of range, and
+    // the result is discarded) takes the branch below
+    double gam = 1.0 / (double)m;
+    const int fb = f0_off[j], fn = f0_off[j + 1] - fb;
+    const int64_t stride = ds.off[j + 1] - ds.off[j];
+    const double* kd = ds.d + ds.base[j] + (i - ds.off[j]);
+    for (int e = 0; e < fn; ++e) {
+      const double w = W[fb + e];
+      const double dv = kd[(int64_t)e * stride];
+      if (w > 0.0) {
+        const double r = dv / w;
+        gam = r > gam ? r : gam;
+      }
+    }
+    p = (double)t * gam;
+    p = p < 1.0 ? p : 1.0;
+    sel = uniform53(seed, (uint64_t)g, kStreamPPS) < p ? 1 : 0;
   } else {
     double gam = 1.0 / (double)m;
     float x[DM];
@@ -462,7 +495,7 @@ __global__ __launch_bounds__(kWave) void k_draw_wide(int sampler, const int32_t*
 void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t* perm,
                  const int32_t* slab, int n, const float* X, int d, const int32_t* csize, int64_t t,
                  uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
-                 double* p_gid, int32_t* flag) {
+                 double* p_gid, int32_t* flag, DistStore ds) {
   if (DM == kWideDM) {
 #define SILH_DW(MM) hipLaunchKernelGGL(k_draw_wide<MM>, dim3((int)ceil_div(n, kWave)), dim3(kWave), 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag)
     switch (metric) {
@@ -475,7 +508,7 @@ void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t*
     return;
   }
   SILH_P1_DISPATCH(k_draw, dim3((int)ceil_div(n, 256)), sampler, perm, slab, n, X, d, csize, t, seed,
-                   f0_off, f0X, W, p_gid, flag);
+                   f0_off, f0X, W, p_gid, flag, ds);
 }
 
 // exact silhouette: every element kept with p = 1

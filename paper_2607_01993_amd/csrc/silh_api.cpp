@@ -114,6 +114,8 @@ struct silh_ctx {
   int32_t *f0_off = nullptr, *f0_cl = nullptr, *items = nullptr, *citem_first = nullptr,
           *citem_count = nullptr, *imeta = nullptr;
   int64_t* ibase = nullptr;
+  int64_t* dbase = nullptr;
+  double* dkeep = nullptr;   // member-to-F0 distances kept by the W pass for the draw
   int* p1_status = nullptr;  // capacity bits of the device-built W work items
   int p1_status_h = 0;
   int64_t *f0_gid = nullptr, *gid_view = nullptr;
@@ -593,7 +595,8 @@ silh_status sample_stage_buffers(silh_ctx* c) {
   c->state = 0;
   c->f0_gid = c->gid_view = nullptr;
   c->f0_cl = c->items = c->citem_first = c->citem_count = c->gid_pk = c->imeta = nullptr;
-  c->ibase = nullptr;
+  c->ibase = c->dbase = nullptr;
+  c->dkeep = nullptr;
   c->p1_status = nullptr;
   c->f0X = c->W0 = c->partial = nullptr;
   c->w32 = c->aux32 = c->Y32 = c->mu = c->bnorm = nullptr;
@@ -644,17 +647,22 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
     const int64_t f0_cap = std::min<int64_t>(n, 64 * (int64_t)k + 1024);
     const int64_t items_cap = ceil_div(n, chunk) + k;
     const int64_t part_cap = std::min<int64_t>((int64_t)1 << 30, items_cap * 64);
+    // the W pass keeps its distances for the draw when they fit (rows of
+    // d > 128 are evaluated again: their kernels keep nothing)
+    const int64_t dist_cap = c->DM > 128 ? 0 : dist_capacity(n, std::log(5.0 * (double)k / c->prm.delta));
     {
       Carve cv;
       cv.add(&c->f0_gid, (size_t)f0_cap).add(&c->f0_cl, (size_t)f0_cap).add(&c->f0X, (size_t)f0_cap * c->DM);
       cv.add(&c->W0, (size_t)f0_cap).add(&c->items, (size_t)items_cap * 6).add(&c->citem_first, (size_t)k);
       cv.add(&c->citem_count, (size_t)k).add(&c->partial, (size_t)part_cap).add(&c->ibase, (size_t)k);
-      cv.add(&c->imeta, 1).add(&c->p1_status, 1);
+      cv.add(&c->imeta, 2).add(&c->p1_status, 1);
+      if (dist_cap > 0) cv.add(&c->dbase, (size_t)k).add(&c->dkeep, (size_t)dist_cap);
       CHK(cv.commit(c, c->alloc_sample));
     }
     HIPCHK(hipMemsetAsync(c->p1_status, 0, sizeof(int), c->st));
     launch_f0_items(c->st, c->csize, c->off, c->f0_off, k, c->t, chunk, (int)f0_cap, part_cap, (int)items_cap,
-                    c->citem_first, c->citem_count, c->ibase, c->imeta, c->items, c->p1_status);
+                    c->citem_first, c->citem_count, c->ibase, c->imeta, c->items, c->p1_status, c->dbase,
+                    dist_cap);
     HIPCHK(hipGetLastError());
     {
       Launch L(c, K_F0_PACK);
@@ -708,10 +716,18 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
       CHK(h2d(c, c->citem_count, c->citem_count_h));
     }
   }
+  DistStore ds;
+  if (c->dkeep != nullptr) {
+    ds.d = c->dkeep;
+    ds.base = c->dbase;
+    ds.off = c->off;
+    ds.use = c->imeta + 1;
+  }
   if (pps && nitems > 0 && f0_rows > 0) {
     {
       Launch L(c, K_W_PARTIAL);
-      launch_w_partial(c->st, c->prm.metric, c->DM, c->items, nitems, c->perm, c->X, d, c->f0X, c->partial);
+      launch_w_partial(c->st, c->prm.metric, c->DM, c->items, nitems, c->perm, c->X, d, c->f0X, c->partial,
+                       ds);
       CHK(L.done());
     }
     {
@@ -724,7 +740,7 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
   {
     Launch L(c, K_DRAW);
     launch_draw(c->st, c->prm.metric, c->DM, pps ? 0 : 1, c->perm, c->slab, n, c->X, d, c->csize, c->t,
-                c->prm.seed, c->f0_off, c->f0X, c->W0, c->p_gid, c->flag);
+                c->prm.seed, c->f0_off, c->f0X, c->W0, c->p_gid, c->flag, ds);
     CHK(L.done());
   }
   if (pps && !host_items) {

@@ -39,6 +39,8 @@ struct Branch {
   double *f0X = nullptr, *W0 = nullptr, *partial = nullptr;
   int32_t *items = nullptr, *citem_first = nullptr, *citem_count = nullptr, *meta = nullptr;
   int64_t* ibase = nullptr;
+  int64_t* dbase = nullptr;
+  double* dkeep = nullptr;
   int64_t* gid_view = nullptr;
   int32_t* gid_pk = nullptr;
   float *w32 = nullptr, *aux32 = nullptr, *Y32 = nullptr, *mu = nullptr, *bnorm = nullptr;
@@ -58,7 +60,7 @@ struct silh_graph {
   std::vector<int64_t> ts;  // Algorithm 1's t of each clustering (k enters it when derived from eps)
   int K = 0, n = 0, d = 0, DM = 0, KP = 0, mprec = 0, p2_rows = 0, chunk = 0, kmax = 0;
   bool mfma = false;
-  int64_t S_cap = 0, F0_cap = 0, items_cap = 0, part_cap = 0;
+  int64_t S_cap = 0, F0_cap = 0, items_cap = 0, part_cap = 0, dist_cap = 0;
   std::vector<Branch> br;
   std::vector<void*> allocs;
   int64_t bytes = 0;
@@ -133,7 +135,7 @@ bool alloc_branch(silh_graph* g, Branch& b) {
             take(g, b.cnt, k) && take(g, b.p_gid, n) && take(g, b.f0_gid, F0) && take(g, b.f0_cl, F0) &&
             take(g, b.f0X, F0 * DM) && take(g, b.W0, F0) && take(g, b.partial, g->part_cap) &&
             take(g, b.items, g->items_cap * 6) && take(g, b.citem_first, k) && take(g, b.citem_count, k) &&
-            take(g, b.meta, 1) && take(g, b.ibase, k) && take(g, b.gid_view, S) && take(g, b.gid_pk, S) &&
+            take(g, b.meta, 2) && take(g, b.ibase, k) && take(g, b.gid_view, S) && take(g, b.gid_pk, S) &&
             take(g, b.w32, S) && take(g, b.aux32, S) && take(g, b.Y32, S * DM) &&
             take(g, b.bpart, ceil_div(n, g->p2_rows));
   if (ok && g->mfma) {
@@ -143,6 +145,7 @@ bool alloc_branch(silh_graph* g, Branch& b) {
     b.Ym = ym;
   }
   if (ok && !g->mfma && phase2_valu_split(g->base.metric, g->DM)) ok = take(g, b.Wpart, n * k);
+  if (ok && g->dist_cap > 0) ok = take(g, b.dbase, k) && take(g, b.dkeep, g->dist_cap);
   return ok;
 }
 
@@ -157,6 +160,13 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
   const int metric = g->base.metric;
   const bool pps = g->base.sampler == SILH_PPS;
   const hipStream_t st = b.st;
+  DistStore ds;
+  if (b.dkeep != nullptr) {
+    ds.d = b.dkeep;
+    ds.base = b.dbase;
+    ds.off = b.off;
+    ds.use = b.meta + 1;
+  }
   // cluster index (perm and slab start at 0 so that rows a bad label leaves
   // unwritten still name a valid element)
   launch_fill_i32(st, b.status, 1, 0);
@@ -172,16 +182,16 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
     launch_scan(st, b.flag, n, b.pos, b.scan_tmp);
     launch_gather_at(st, b.pos, b.off, k, b.f0_off);
     launch_f0_items(st, b.csize, b.off, b.f0_off, k, t, g->chunk, (int)g->F0_cap, g->part_cap, (int)g->items_cap,
-                    b.citem_first, b.citem_count, b.ibase, b.meta, b.items, b.status);
+                    b.citem_first, b.citem_count, b.ibase, b.meta, b.items, b.status, b.dbase, g->dist_cap);
     launch_f0_pack(st, b.perm, b.slab, b.flag, b.pos, n, g->X, d, DM, (int)g->F0_cap, b.f0_gid, b.f0_cl, b.f0X);
-    launch_w_partial(st, metric, DM, b.items, (int)g->items_cap, b.perm, g->X, d, b.f0X, b.partial);
+    launch_w_partial(st, metric, DM, b.items, (int)g->items_cap, b.perm, g->X, d, b.f0X, b.partial, ds);
     launch_w_final(st, b.f0_cl, (int)g->F0_cap, b.f0_off, k, b.citem_first, b.citem_count, b.items, b.partial,
                    b.W0);
   } else {
     launch_fill_i32(st, b.f0_off, k + 1, 0);
   }
   launch_draw(st, metric, DM, pps ? 0 : 1, b.perm, b.slab, n, g->X, d, b.csize, t, g->base.seed, b.f0_off, b.f0X,
-              b.W0, b.p_gid, b.flag);
+              b.W0, b.p_gid, b.flag, pps ? ds : DistStore{});
   // compaction and packing
   launch_scan(st, b.flag, n, b.pos, b.scan_tmp);
   launch_gather_at(st, b.pos, b.off, k, b.s_off);
@@ -285,6 +295,10 @@ silh_status silh_graph_create(const silh_params* base, const float* X, const int
   g->F0_cap = std::min<int64_t>(g->n, 64 * (int64_t)g->kmax + 1024);
   g->items_cap = ceil_div(g->n, g->chunk) + g->kmax;
   g->part_cap = std::min<int64_t>((int64_t)1 << 30, g->items_cap * 64);
+  // member distances kept by the W pass for the draw (d <= 128; the largest k)
+  g->dist_cap = (base->sampler == SILH_PPS && g->DM <= 128)
+                    ? dist_capacity(g->n, std::log(5.0 * (double)g->kmax / base->delta))
+                    : 0;
   g->br.resize((size_t)chains);
   bool ok = take(g, g->means_d, K) && take(g, g->status_d, K);
   for (Branch& b : g->br) ok = ok && alloc_branch(g, b);

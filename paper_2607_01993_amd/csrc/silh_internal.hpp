@@ -44,11 +44,24 @@ void launch_f0_flag(hipStream_t st, const int32_t* perm, const int32_t* slab, in
 void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
                     const int32_t* pos, int n, const float* X, int d, int DM, int cap, int64_t* f0_gid,
                     int32_t* f0_cl, double* f0X);
+// float64 distances from the members of each cluster to its initial-sample
+// rows, kept by the W pass for the draw (which then reads them instead of
+// evaluating them again): the distance of the member at sorted position i of
+// cluster j to F0_j's e-th row is at d[base[j] + e |C_j| + (i - off[j])].
+// With d null, or *use == 0 (set on the device when the distances did not fit
+// their capacity), nothing is kept and the draw evaluates the distances.
+struct DistStore {
+  double* d = nullptr;
+  const int64_t* base = nullptr;  // [k]
+  const int32_t* off = nullptr;   // [k + 1] cluster offsets
+  const int32_t* use = nullptr;   // device flag
+};
 // one block per work item: item = (cluster, first sorted pos, end sorted pos,
 // first F0 index of the cluster, |F0_j|, base in `partial`)
 // f0X rows have stride DM (zero-padded)
 void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, int nitems,
-                      const int32_t* perm, const float* X, int d, const double* f0X, double* partial);
+                      const int32_t* perm, const float* X, int d, const double* f0X, double* partial,
+                      DistStore ds = {});
 // F0 blocks at most; those at or past f0_off[k] return at once
 void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t* f0_off, int k,
                     const int32_t* citem_first, const int32_t* citem_count, const int32_t* items,
@@ -56,7 +69,7 @@ void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t*
 void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t* perm,
                  const int32_t* slab, int n, const float* X, int d, const int32_t* csize, int64_t t,
                  uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
-                 double* p_gid, int32_t* flag);
+                 double* p_gid, int32_t* flag, DistStore ds = {});
 void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, int32_t* flag);
 // Scatter the selected elements into the cluster-blocked, padded sample.
 // mode 0: raw coordinates; 1: rows scaled to unit L2 norm (cosine).  Rows at
@@ -130,10 +143,16 @@ void launch_fill_i32(hipStream_t st, int32_t* p, int64_t count, int32_t v);
 void launch_index_sizes(hipStream_t st, const int32_t* csize, int k, double lnterm, int32_t* off, double* q,
                         int* status);
 // clamps f0_off to f0_cap and writes the W work items (items_cap slots, the
-// unused ones empty), per-cluster first item / count and partial bases
+// unused ones empty), per-cluster first item / count and partial bases;
+// with dbase non-null also the bases of the kept distances (DistStore) and
+// meta[1] = 1 when they fit dist_cap doubles
 void launch_f0_items(hipStream_t st, const int32_t* csize, const int32_t* off, int32_t* f0_off, int k,
                      int64_t t, int chunk, int f0_cap, int64_t part_cap, int items_cap, int32_t* citem_first,
-                     int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status);
+                     int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status,
+                     int64_t* dbase = nullptr, int64_t dist_cap = 0);
+// capacity (doubles) of the kept distances for n elements, k clusters and
+// ln(5k/delta): about 1.25 times their expected count, at most 2^27
+int64_t dist_capacity(int64_t n, double lnterm);
 // cnt[j] = |F_j|, sp_off = offsets of the blocks padded to kSamplePad rows
 void launch_sample_sizes(hipStream_t st, const int32_t* s_off, int k, int s_cap, int32_t* cnt, int32_t* sp_off,
                          int* status);

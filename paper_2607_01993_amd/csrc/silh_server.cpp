@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -112,8 +114,9 @@ struct silh_server {
 namespace {
 
 // Device bytes one request needs at most, roughly: the cluster index and the
-// Phase-1 arrays (about 24 bytes per element) plus the packed sample, sized
-// for S = 2 k t + 32 k rows (a few times the expected 1-1.5 k t).
+// Phase-1 arrays (about 24 bytes per element), the distances kept between the
+// W pass and the draw, plus the packed sample, sized for S = 2 k t + 32 k rows
+// (a few times the expected 1-1.5 k t).
 uint64_t estimate_bytes(const Dataset& ds, const silh_request& r) {
   const int DM = silh::dm_for(ds.d);
   const uint64_t n = (uint64_t)ds.n;
@@ -126,7 +129,12 @@ uint64_t estimate_bytes(const Dataset& ds, const silh_request& r) {
   const uint64_t m = r.m > 0 ? (uint64_t)r.m : 0;  // row draws: ids, gathered rows, outputs
   // d > 128 Manhattan / Canberra: float64 partial sums per element and cluster
   const uint64_t split = (DM > 128 && (r.metric == SILH_MANH || r.metric == SILH_CANB)) ? n * (uint64_t)r.k * 8 : 0;
-  return 24 * n + S * row + m * ((uint64_t)ds.d * 4 + 32) + split + ((uint64_t)1 << 20);
+  // PPS with d <= 128: the W pass keeps its distances for the draw (allocated
+  // at their capacity)
+  const uint64_t kept = (r.sampler == SILH_PPS && DM <= 128)
+                            ? 8 * (uint64_t)silh::dist_capacity((int64_t)n, std::log(5.0 * r.k / r.delta))
+                            : 0;
+  return 24 * n + S * row + m * ((uint64_t)ds.d * 4 + 32) + split + kept + ((uint64_t)1 << 20);
 }
 
 void run_job(Dataset ds, const silh_request& r, Pool& pool, hipStream_t st, silh_result& res) {

@@ -1,6 +1,8 @@
 """The serving runtime (include/silh_server.h) on the GPU: results of requests
 run concurrently by the server equal those of the same requests run alone
 through silh.h; admission, argument checks and per-request failures."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -59,9 +61,13 @@ def test_server_admission_under_a_small_budget():
     and never more than one runs at once (start after the previous done)."""
     ds = _datasets()
     X, L, k = ds[0]
-    # the estimate of one such request is 24 n + (a few KB of sample) + 1 MiB:
-    # 1.5 times its main part fits one request, never two
-    srv = native.Server(workers=4, hbm_budget_bytes=int(1.5 * (24 * X.shape[0] + (1 << 20))))
+    # the estimate of one such request is 24 n + the distances kept between
+    # the W pass and the draw (their capacity, n (2.5 ln(5k/delta) + 8)
+    # doubles) + (a few KB of sample) + 1 MiB: 1.5 times its main part fits
+    # one request, never two
+    n = X.shape[0]
+    kept = 8 * int(min(n * (2.5 * math.log(5.0 * k / 0.01) + 8.0), 2 ** 27))
+    srv = native.Server(workers=4, hbm_budget_bytes=int(1.5 * (24 * n + kept + (1 << 20))))
     did = srv.add_dataset(X)
     tks = [srv.submit(did, L, k, "eucl", "bf16", t=32, seed=s) for s in range(6)]
     res = [srv.wait(tk) for tk in tks]
