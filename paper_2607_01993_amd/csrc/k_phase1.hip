@@ -372,6 +372,8 @@ void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t*
 // gamma_e, p_e and the final Poisson draw (PPS), or the uniform rate t/|C_j|.
 // Clusters with |C_j| <= t are taken whole with p = 1.
 // ----------------------------------------------------------------------------
+constexpr int kDrawB = 8;  // kept distances loaded together by the draw
+
 template <int M, int DM>
 __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __restrict__ perm,
                                               const int32_t* __restrict__ slab, int n,
@@ -405,12 +407,23 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
     const int fb = f0_off[j], fn = f0_off[j + 1] - fb;
     const int64_t stride = ds.off[j + 1] - ds.off[j];
     const double* kd = ds.d + ds.base[j] + (i - ds.off[j]);
-    for (int e = 0; e < fn; ++e) {
-      const double w = W[fb + e];
-      const double dv = kd[(int64_t)e * stride];
-      if (w > 0.0) {
-        const double r = dv / w;
-        gam = r > gam ? r : gam;
+    // kDrawB weights and distances are loaded before any is used, so their
+    // latencies overlap; past the end the last element is repeated, which
+    // leaves the maximum unchanged
+    for (int e0 = 0; e0 < fn; e0 += kDrawB) {
+      double wv[kDrawB], dv[kDrawB];
+#pragma unroll
+      for (int e = 0; e < kDrawB; ++e) {
+        const int ee = e0 + e < fn ? e0 + e : fn - 1;
+        wv[e] = W[fb + ee];
+        dv[e] = kd[(int64_t)ee * stride];
+      }
+#pragma unroll
+      for (int e = 0; e < kDrawB; ++e) {
+        if (wv[e] > 0.0) {
+          const double r = dv[e] / wv[e];
+          gam = r > gam ? r : gam;
+        }
       }
     }
     p = (double)t * gam;
