@@ -74,8 +74,9 @@ void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* co
 }
 
 // One wave per unit walks its rows in order, 64 at a time.  Lanes holding the
-// same label get consecutive ranks in lane order (ballot + popcount), so the
-// order is stable: ids ascend inside each cluster.  The unit's rows are first
+// same label (found by one ballot per label bit) get consecutive ranks in lane
+// order (popcount of the lower such lanes), so the order is stable: ids ascend
+// inside each cluster.  The unit's rows are first
 // placed in LDS grouped by label (the unit's own label offsets), then each
 // label's run is written to its global range in one contiguous piece.
 // LDS: base[k] (global start of the unit's run of label j), loc[k] (next local
@@ -129,25 +130,28 @@ __global__ __launch_bounds__(64) void k_scatter(const int32_t* __restrict__ labe
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // bits of a label in [0, k)
+  const int kb = k > 1 ? 32 - __clz(k - 1) : 0;
   for (int64_t c = b0; c < end; c += 64) {
     const int64_t i = c + lane;
     const int L = i < end ? labels[i] : -1;
     const bool valid = (unsigned)L < (unsigned)k;
-    uint64_t active = __ballot(valid);
-    while (active) {
-      const int leader = __ffsll((unsigned long long)active) - 1;
-      const int Ll = __shfl(L, leader, 64);
-      const uint64_t mask = __ballot(valid && L == Ll);
-      if (valid && L == Ll) {
-        const int slot = loc[Ll] + __popcll(mask & lt);
-        ids[slot] = (int32_t)i;
-        lab[slot] = Ll;
-      }
-      __syncthreads();
-      if (lane == leader) loc[Ll] += __popcll(mask);
-      __syncthreads();
-      active &= ~mask;
+    // the lanes holding this lane's label: one ballot per label bit
+    uint64_t same = __ballot(valid);
+    for (int bit = 0; bit < kb; ++bit) {
+      const bool one = (L >> bit) & 1;
+      const uint64_t ones = __ballot(valid && one);
+      same &= one ? ones : ~ones;
     }
+    if (valid) {
+      const int slot = loc[L] + __popcll(same & lt);
+      ids[slot] = (int32_t)i;
+      lab[slot] = L;
+    }
+    __syncthreads();
+    // the lowest lane of each label advances that label's slot
+    if (valid && (same & lt) == 0) loc[L] += __popcll(same);
+    __syncthreads();
   }
   __syncthreads();
   // loc[j] is now the end of label j's local run; its start is loc[j] - count.
@@ -175,20 +179,59 @@ void launch_scatter(hipStream_t st, const int32_t* labels, int n, int k, int seg
 // int32 exclusive scan: per-tile sums, a single-block scan of the tile sums,
 // then per-tile scans offset by the tile base.
 // ----------------------------------------------------------------------------
+__global__ void k_fill_zero1(int32_t* __restrict__ out) { out[0] = 0; }
+
+// eight consecutive values of a tile (zero past n): two 16-byte loads when
+// all eight are in range and the array is 16-byte aligned
+__device__ __forceinline__ void scan_load8(const int32_t* __restrict__ in, int64_t base, int n, bool vec,
+                                           int32_t (&v)[8]) {
+  if (vec && base + 8 <= n) {
+    const int4 a = *(const int4*)(in + base);
+    const int4 b = *(const int4*)(in + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = base + i < n ? in[base + i] : 0;
+  }
+}
+
+// exclusive prefix of s over the 256 threads of a block (wave scans by
+// shuffles, then the four wave totals); *tot receives the block's total
+__device__ __forceinline__ int32_t block_excl_256(int32_t s, int32_t* __restrict__ wtot, int32_t* tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wtot[wid] = incl;
+  __syncthreads();
+  int32_t pre = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) pre += w < wid ? wtot[w] : 0;
+  *tot = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  return pre + incl - s;
+}
+
 __global__ __launch_bounds__(256) void k_scan_reduce(const int32_t* __restrict__ in, int n,
                                                      int32_t* __restrict__ tsum) {
   __shared__ int32_t sh[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  const bool vec = ((uintptr_t)in & 15) == 0;
+  int32_t v[8];
+  scan_load8(in, base, n, vec, v);
   int32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-    if (base + i < n) s += in[base + i];
+  for (int i = 0; i < 8; ++i) s += v[i];
   s = wave_sum_i32(s);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) tsum[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// exclusive scan of the tile sums in place (one block), tsum[nt] = total
 __global__ __launch_bounds__(1024) void k_scan_tiles(int32_t* __restrict__ tsum, int nt) {
   __shared__ int32_t part[1024];
   const int per = (nt + 1023) / 1024;
@@ -213,40 +256,76 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int32_t* __restrict__ tsum,
   if (threadIdx.x == 1023) tsum[nt] = part[1023];
 }
 
+// out[i] = tile prefix + the exclusive scan inside the tile.  FUSED: the tile
+// prefix is the sum of the raw tile sums before this tile (read by the whole
+// block; used while the tiles are few), and the last tile writes out[n];
+// otherwise tsum holds the scanned tile sums and tsum[nt] the total.
+template <bool FUSED>
 __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ in, int n,
                                                     const int32_t* __restrict__ tsum, int nt,
                                                     int32_t* __restrict__ out) {
-  __shared__ int32_t part[256];
+  __shared__ int32_t wtot[4];
+  __shared__ int32_t red[4];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  const bool vec = ((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 15) == 0;
   int32_t v[8];
+  scan_load8(in, base, n, vec, v);
   int32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0;
-    s += v[i];
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    int32_t u = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+  for (int i = 0; i < 8; ++i) s += v[i];
+  int32_t tpre;
+  if constexpr (FUSED) {
+    int32_t a = 0;
+    for (int q = threadIdx.x; q < (int)blockIdx.x; q += 256) a += tsum[q];
+    a = wave_sum_i32(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    part[threadIdx.x] += u;
-    __syncthreads();
+    tpre = red[0] + red[1] + red[2] + red[3];
+  } else {
+    tpre = tsum[blockIdx.x];
   }
-  int32_t run = tsum[blockIdx.x] + (threadIdx.x ? part[threadIdx.x - 1] : 0);
+  int32_t btot;
+  int32_t run = tpre + block_excl_256(s, wtot, &btot);
+  int32_t o[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    if (base + i < n) out[base + i] = run;
+    o[i] = run;
     run += v[i];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tsum[nt];
+  if (vec && base + 8 <= n) {
+    *(int4*)(out + base) = int4{o[0], o[1], o[2], o[3]};
+    *(int4*)(out + base + 4) = int4{o[4], o[5], o[6], o[7]};
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (base + i < n) out[base + i] = o[i];
+  }
+  if (threadIdx.x == 0) {
+    if constexpr (FUSED) {
+      if ((int)blockIdx.x == nt - 1) out[n] = tpre + btot;
+    } else {
+      if (blockIdx.x == 0) out[n] = tsum[nt];
+    }
+  }
 }
+
+// up to this many tiles the tile prefix is summed inside the apply pass
+// (O(nt^2 / 2) L2 reads in all, a few MB at n = 4e6), saving a launch
+constexpr int kScanFusedTiles = 2048;
 
 void launch_scan(hipStream_t st, const int32_t* in, int n, int32_t* out, int32_t* tmp) {
   const int nt = (int)ceil_div(n, kScanTile);
+  if (nt == 0) {
+    hipLaunchKernelGGL(k_fill_zero1, dim3(1), dim3(1), 0, st, out);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(256), 0, st, in, n, tmp);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tmp, nt);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(256), 0, st, in, n, tmp, nt, out);
+  if (nt <= kScanFusedTiles) {
+    hipLaunchKernelGGL(k_scan_apply<true>, dim3(nt), dim3(256), 0, st, in, n, tmp, nt, out);
+  } else {
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tmp, nt);
+    hipLaunchKernelGGL(k_scan_apply<false>, dim3(nt), dim3(256), 0, st, in, n, tmp, nt, out);
+  }
 }
 
 __global__ void k_gather_at(const int32_t* __restrict__ scan, const int32_t* __restrict__ off, int k,
