@@ -152,7 +152,16 @@ __global__ __launch_bounds__(256) void k_f0_pack(const int32_t* __restrict__ per
   f0_cl[dst] = slab[i];
   const float* xr = X + (size_t)g * d;
   double* yr = f0X + (size_t)dst * DM;
-  for (int c = 0; c < DM; ++c) yr[c] = c < d ? (double)xr[c] : 0.0;
+  if ((d & 3) == 0 && ((uintptr_t)X & 15) == 0) {
+    // 16-byte row chunks (DM is a multiple of 8, so the float64 row is too)
+    for (int c = 0; c < DM; c += 4) {
+      const float4 v = c < d ? *(const float4*)(xr + c) : float4{0.f, 0.f, 0.f, 0.f};
+      *(double2*)(yr + c) = double2{(double)v.x, (double)v.y};
+      *(double2*)(yr + c + 2) = double2{(double)v.z, (double)v.w};
+    }
+  } else {
+    for (int c = 0; c < DM; ++c) yr[c] = c < d ? (double)xr[c] : 0.0;
+  }
 }
 
 void launch_f0_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
@@ -565,14 +574,34 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
   w32[dst] = (float)(1.0 / p_gid[g]);
   const float* xr = X + (size_t)g * d;
   float* yr = Y32 + (size_t)dst * DM;
+  const bool vec = (d & 3) == 0 && ((uintptr_t)X & 15) == 0;
   double scale = 1.0;
   if (mode == 1) {
     double s2 = 0.0;
-    for (int c = 0; c < d; ++c) s2 = s2 + (double)xr[c] * (double)xr[c];
+    if (vec) {
+      for (int c = 0; c < d; c += 4) {
+        const float4 v = *(const float4*)(xr + c);
+        s2 = s2 + (double)v.x * (double)v.x;
+        s2 = s2 + (double)v.y * (double)v.y;
+        s2 = s2 + (double)v.z * (double)v.z;
+        s2 = s2 + (double)v.w * (double)v.w;
+      }
+    } else {
+      for (int c = 0; c < d; ++c) s2 = s2 + (double)xr[c] * (double)xr[c];
+    }
     scale = s2 > 0.0 ? 1.0 / __dsqrt_rn(s2) : 0.0;
     aux32[dst] = s2 > 0.0 ? 0.0f : 0.5f;
   }
-  for (int c = 0; c < DM; ++c) yr[c] = c < d ? (float)((double)xr[c] * scale) : 0.0f;
+  if (vec) {
+    // 16-byte row chunks (DM is a multiple of 8)
+    for (int c = 0; c < DM; c += 4) {
+      const float4 v = c < d ? *(const float4*)(xr + c) : float4{0.f, 0.f, 0.f, 0.f};
+      *(float4*)(yr + c) = float4{(float)((double)v.x * scale), (float)((double)v.y * scale),
+                                  (float)((double)v.z * scale), (float)((double)v.w * scale)};
+    }
+  } else {
+    for (int c = 0; c < DM; ++c) yr[c] = c < d ? (float)((double)xr[c] * scale) : 0.0f;
+  }
 }
 
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
