@@ -383,12 +383,15 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
   constexpr int kNCh = 32 * kChRow;
   constexpr int kPer = (kNCh + 255) / 256;
   constexpr bool kLds = P == 2 ? C::HALF > 40 : C::HALF > 30;
-  __shared__ __attribute__((aligned(16))) unsigned char ldsB[kLds ? 2 * kTileB : 16];
-  __shared__ float ldsW[2][32];
-  __shared__ int ldsG[2][32];
-  u32x4 stage[kLds ? kPer : 1];
-  float sw = 0.f;
-  int sg = -1;
+  // tiles per LDS stage (one barrier per stage): two where it costs no wave
+  // per SIMD and measured faster (bf16 at d = 64, fp8), else one
+  constexpr int kTB = (kLds && PB == 1 && (P == 2 || (P == 1 && DM == 64))) ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) unsigned char ldsB[kLds ? 2 * kTB * kTileB : 16];
+  __shared__ float ldsW[2][kTB * 32];
+  __shared__ int ldsG[2][kTB * 32];
+  u32x4 stage[kTB][kLds ? kPer : 1];
+  float sw[kTB] = {};
+  int sg[kTB] = {};
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int col = lane & 31;
@@ -612,33 +615,41 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     };
     if constexpr (kLds) {
       // Long rows: the block's four waves sweep the same tiles, so each tile
-      // is loaded once per block into LDS (double-buffered: tile t + 1 is
-      // fetched into registers while tile t is computed, then stored to the
-      // other buffer), and every wave reads its B fragment from there.
+      // is loaded once per block into LDS and every wave reads its B fragment
+      // from there.  Tiles go in stages of kTB (one barrier per stage),
+      // double-buffered: stage s + 1 is fetched into registers while stage s
+      // is computed, then stored to the other buffer.
       auto fetch = [&](int row0) {
-        const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)row0 * (size_t)kRowB, 32 * kRowB);
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-          const int ci = threadIdx.x + 256 * i;
-          stage[i] = ci < kNCh ? __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)ci, 0, 0) : u32x4{};
-        }
-        if (threadIdx.x < 32) {
-          sw = w[row0 + threadIdx.x];
-          sg = P == 2 ? __float_as_int(bnorm[row0 + threadIdx.x]) : gid_pk[row0 + threadIdx.x];
+        for (int tt = 0; tt < kTB; ++tt) {
+          const int r0 = clamp_row(row0 + 32 * tt);
+          const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)r0 * (size_t)kRowB, 32 * kRowB);
+#pragma unroll
+          for (int i = 0; i < kPer; ++i) {
+            const int ci = threadIdx.x + 256 * i;
+            stage[tt][i] = ci < kNCh ? __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)ci, 0, 0) : u32x4{};
+          }
+          if (threadIdx.x < 32) {
+            sw[tt] = w[r0 + threadIdx.x];
+            sg[tt] = P == 2 ? __float_as_int(bnorm[r0 + threadIdx.x]) : gid_pk[r0 + threadIdx.x];
+          }
         }
       };
       auto store = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-          const int ci = threadIdx.x + 256 * i;
-          if (ci < kNCh) {
-            const int r = ci / kChRow, q = ci - r * kChRow;
-            *(u32x4*)(ldsB + buf * kTileB + r * kLRow + 16 * q) = stage[i];
+        for (int tt = 0; tt < kTB; ++tt) {
+#pragma unroll
+          for (int i = 0; i < kPer; ++i) {
+            const int ci = threadIdx.x + 256 * i;
+            if (ci < kNCh) {
+              const int r = ci / kChRow, q = ci - r * kChRow;
+              *(u32x4*)(ldsB + (buf * kTB + tt) * kTileB + r * kLRow + 16 * q) = stage[tt][i];
+            }
           }
-        }
-        if (threadIdx.x < 32) {
-          ldsW[buf][threadIdx.x] = sw;
-          ldsG[buf][threadIdx.x] = sg;
+          if (threadIdx.x < 32) {
+            ldsW[buf][32 * tt + threadIdx.x] = sw[tt];
+            ldsG[buf][32 * tt + threadIdx.x] = sg[tt];
+          }
         }
       };
       if (ntile > 0 && pre != base) {  // block-uniform: every wave sweeps the same clusters
@@ -647,22 +658,29 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         pre = base;
         __syncthreads();
       }
-      for (int t = 0; t < ntile; ++t) {
+      for (int t = 0; t < ntile; t += kTB) {
         const int buf = cb;
-        const int nrow = clamp_row(base + (t + 1) * 32);
+        // the next stage: this cluster's next tiles, or after its last stage
+        // the next cluster's first tiles
+        const int nrow = clamp_row(t + kTB < ntile ? base + (t + kTB) * 32 : base + ntile * 32);
         fetch(nrow);
-        const unsigned char* tl = ldsB + buf * kTileB + col * kLRow + h * C::HALF * C::ELEM;
-        auto fromLds = [&](int q) {
-          if constexpr (P == 0) {
-            return *(const float2*)(tl + 8 * q);
-          } else if constexpr (P == 1) {
-            return *(const bf16x8*)(tl + 16 * q);
-          } else {
-            const u32x4 lo = *(const u32x4*)(tl + 32 * q), hi = *(const u32x4*)(tl + 32 * q + 16);
-            return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+#pragma unroll
+        for (int tt = 0; tt < kTB; ++tt) {
+          if (t + tt < ntile) {  // block-uniform
+            const unsigned char* tl = ldsB + (buf * kTB + tt) * kTileB + col * kLRow + h * C::HALF * C::ELEM;
+            auto fromLds = [&](int q) {
+              if constexpr (P == 0) {
+                return *(const float2*)(tl + 8 * q);
+              } else if constexpr (P == 1) {
+                return *(const bf16x8*)(tl + 16 * q);
+              } else {
+                const u32x4 lo = *(const u32x4*)(tl + 32 * q), hi = *(const u32x4*)(tl + 32 * q + 16);
+                return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+              }
+            };
+            tile(fromLds, ldsW[buf][32 * tt + col], ldsG[buf][32 * tt + col], t + tt + 1 == ntile);
           }
-        };
-        tile(fromLds, ldsW[buf][col], ldsG[buf][col], t + 1 == ntile);
+        }
         store(buf ^ 1);
         __syncthreads();
         cb = buf ^ 1;
