@@ -120,7 +120,8 @@ def run_steps(native, Xd, Ld, k, metric, prec, t, seed, steps, warmup, out_a, ou
     info = {}
 
     def step(prof):
-        ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, "pps", t=t, delta=0.01, seed=seed)
+        ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, "pps", t=t, delta=0.01, seed=seed,
+                                      use_torch_alloc=False)
         if prof:
             native.silh_prof_enable(ctx, prof)
         S, _ = native.silh_pps_sample(ctx)
@@ -164,7 +165,8 @@ def run_rows(native, torch, Xd, Ld, k, metric, prec, t, seed, steps, full_mean, 
     for i in range(steps + 1):
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, "pps", t=t, delta=0.01, seed=seed)
+        ctx = native.silh_sample_init(Xd, Ld, k, metric, prec, "pps", t=t, delta=0.01, seed=seed,
+                                      use_torch_alloc=False)
         S, _ = native.silh_pps_sample(ctx)
         rows = native.silh_draw_rows(seed + 1000, n, m)
         mean = native.silh_scores_rows(ctx, rows, a=False, b=False, s=False, mean=True)["mean"]

@@ -71,7 +71,10 @@ typedef enum { SILH_PPS = 0, SILH_UNI = 1 } silh_sampler;
 /* Device-memory allocator hooks.  alloc must return device memory of at least
  * `bytes` bytes, usable on the context's stream, or NULL on failure (the call
  * then fails with SILH_E_NOMEM).  free receives every pointer alloc returned,
- * exactly once.  If alloc is NULL the library uses hipMalloc / hipFree. */
+ * exactly once.  If alloc is NULL the library takes blocks from a cache it
+ * keeps per (device, stream) until the process ends (new blocks by
+ * hipMalloc; a freed block is reused only by later allocations on the same
+ * stream, so no call synchronises the device once the cache is warm). */
 typedef void* (*silh_alloc_fn)(size_t bytes, void* user);
 typedef void (*silh_free_fn)(void* ptr, void* user);
 

@@ -145,14 +145,52 @@ struct silh_ctx {
 
 namespace {
 
+// Without an allocator callback, device memory comes from a cache of blocks
+// the library keeps per (device, stream) until the process ends: a block
+// freed by a context goes back to its stream's list, and a later allocation
+// on the same stream takes the smallest cached block of at least the size
+// asked for and at most twice it.  Work on one stream runs in order, so the
+// next user of a block starts after the previous one's last kernel; no call
+// synchronises the device once the cache is warm.  New blocks: hipMalloc.
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+};
+std::mutex g_dcache_mu;
+std::map<std::pair<int, hipStream_t>, std::vector<CachedBlock>> g_dcache;
+std::map<void*, std::pair<std::pair<int, hipStream_t>, size_t>> g_dlive;
+
 void* raw_alloc(silh_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (c->prm.alloc) return c->prm.alloc(bytes, c->prm.alloc_user);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const auto key = std::make_pair(dev, c->st);
+  {
+    std::lock_guard<std::mutex> lk(g_dcache_mu);
+    auto& v = g_dcache[key];
+    size_t best = v.size();
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i].bytes >= bytes && v[i].bytes / 2 <= bytes && (best == v.size() || v[i].bytes < v[best].bytes))
+        best = i;
+    if (best < v.size()) {
+      const CachedBlock b = v[best];
+      v[best] = v.back();
+      v.pop_back();
+      g_dlive[b.p] = {key, b.bytes};
+      return b.p;
+    }
+  }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
+  std::lock_guard<std::mutex> lk(g_dcache_mu);
+  g_dlive[p] = {key, bytes};
   return p;
 }
 
@@ -160,9 +198,13 @@ void raw_free(silh_ctx* c, void* p) {
   if (!p) return;
   if (c->prm.alloc) {
     if (c->prm.free) c->prm.free(p, c->prm.alloc_user);
-  } else {
-    (void)hipFree(p);
+    return;
   }
+  std::lock_guard<std::mutex> lk(g_dcache_mu);
+  auto it = g_dlive.find(p);
+  if (it == g_dlive.end()) return;  // not ours
+  g_dcache[it->second.first].push_back({p, it->second.second});
+  g_dlive.erase(it);
 }
 
 // Buffers of one stage are carved out of a single allocation (one allocator
