@@ -210,18 +210,15 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
 // 16 per-lane row sums, each over the lane's column: five exchange steps, each
 // pairing lanes that differ in one bit of the column index and halving the
 // number of live values (the partner receives the half it keeps).  Partners:
-// lane ^ 16 by ds_swizzle, then within 16-lane rows by DPP (rotate by 8,
-// mirror inside 8, quad permutations), which pair lanes that differ in bit 3,
-// bit 2, bit 1 and bit 0 respectively.  Afterwards lane l holds the sum over
-// all 32 columns for row r = (l >> 1) & 15 of its half (lanes l and l^1 agree).
+// lane ^ 16 by a row swap between two registers, then within 16-lane rows by
+// DPP (rotate by 8, mirror inside 8, quad permutations), which pair lanes
+// that differ in bit 3, bit 2, bit 1 and bit 0 respectively.  Afterwards lane
+// l holds the sum over all 32 columns for row r = (l >> 1) & 15 of its half
+// (lanes l and l^1 agree).
 // ----------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float swz_xor16(float v) {
-  // BitMode swizzle inside 32 lanes: and 0x1f, or 0, xor 0x10
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
 }
 constexpr int kDppRor8 = 0x128;        // row_ror:8      -> lane ^ 8 inside 16
 constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: 7 - (lane & 7)
@@ -230,12 +227,13 @@ constexpr int kDppQuad1032 = 0xB1;     // quad_perm [1,0,3,2] -> lane ^ 1
 
 __device__ __forceinline__ float transpose_reduce16(float (&v)[16], int lane) {
   {
-    const bool up = lane & 16;
+    // lane ^ 16: v_permlane16_swap exchanges the odd 16-lane rows of v[i]
+    // with the even rows of v[i + 8], leaving every lane both copies of the
+    // value it keeps (v[i] below lane 16 of each half, v[i + 8] above)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const float send = up ? v[i] : v[i + 8];
-      const float keep = up ? v[i + 8] : v[i];
-      v[i] = keep + swz_xor16(send);
+      const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
+      v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
   }
   {
