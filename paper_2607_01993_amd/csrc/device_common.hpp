@@ -62,25 +62,6 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
-// The unit-length form of a float32 row, as the sample packing forms it:
-// the squared norm in float64 over the d coordinates in order, one rounding
-// per operation; the row times 1 / sqrt of it, each coordinate rounded once
-// to float32 by unit_coord.  *zero = the row is all zeros (the cosine reading
-// then makes its distance 1 to everything).  The same steps on both sides
-// make identical rows identical unit vectors, so their distance is exactly 0.
-__device__ __forceinline__ double unit_scale(const float* __restrict__ row, int d, bool* zero) {
-  double s2 = 0.0;
-  for (int c = 0; c < d; ++c) {
-    const double v = (double)row[c];
-    s2 = __dadd_rn(s2, __dmul_rn(v, v));
-  }
-  *zero = !(s2 > 0.0);
-  return s2 > 0.0 ? 1.0 / __dsqrt_rn(s2) : 0.0;
-}
-__device__ __forceinline__ float unit_coord(float x, double scale) {
-  return (float)__dmul_rn((double)x, scale);
-}
-
 __device__ __forceinline__ int wave_sum_i32(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

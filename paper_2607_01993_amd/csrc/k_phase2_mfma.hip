@@ -429,15 +429,13 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
         p = fmaf(xc[e], xc[e], p);
       }
     }
-    (void)p;
     ux[b] = 0.f;
     if (M == kCos) {
-      // unit rows formed exactly as the packed sample rows are
-      bool zero = false;
-      const double scale = unit_scale(xp, d, &zero);
-      ux[b] = zero ? 0.5f : 0.f;
+      const float s2 = p + __shfl_xor(p, 32, kWave);
+      const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+      ux[b] = s2 > 0.f ? 0.f : 0.5f;
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) xr[b][i] = unit_coord(xr[b][i], scale);
+      for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
     }
     pout[b] = P0 + 32 * b + prow;
     own[b] = labels[pout[b] < n ? pout[b] : n - 1];

@@ -87,12 +87,14 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
 #pragma unroll
   for (int c = 0; c < DM; ++c) x[c] = c0 + c < d ? xr[c] : 0.0f;
   float ux = 0.f;
-  if (M == kCos) {  // unit vector formed as the sample's (zero stays zero, with u = 0.5)
-    bool zero = false;
-    const double scale = unit_scale(X + (size_t)er * d, d, &zero);
-    ux = zero ? 0.5f : 0.f;
+  if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
+    float s2 = 0.f;
 #pragma unroll
-    for (int c = 0; c < DM; ++c) x[c] = unit_coord(x[c], scale);
+    for (int c = 0; c < DM; ++c) s2 = fmaf(x[c], x[c], s2);
+    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+    ux = s2 > 0.f ? 0.f : 0.5f;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) x[c] *= rx;
   }
   const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
 
@@ -158,13 +160,17 @@ __global__ __launch_bounds__(kWave) void k_p2_valu_wide(
   const int er = valid ? e : n - 1;
   float* xl = xs + threadIdx.x;
   const float* xr = X + (size_t)er * d;
-  for (int c = 0; c < kWideDM; ++c) xl[c * kWave] = c < d ? xr[c] : 0.0f;
+  float s2 = 0.f;
+  for (int c = 0; c < kWideDM; ++c) {
+    const float v = c < d ? xr[c] : 0.0f;
+    xl[c * kWave] = v;
+    s2 = fmaf(v, v, s2);
+  }
   float ux = 0.f;
-  if (M == kCos) {  // unit vector formed as the sample's (zero stays zero, with u = 0.5)
-    bool zero = false;
-    const double scale = unit_scale(xr, d, &zero);
-    ux = zero ? 0.5f : 0.f;
-    for (int c = 0; c < kWideDM; ++c) xl[c * kWave] = unit_coord(xl[c * kWave], scale);
+  if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
+    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
+    ux = s2 > 0.f ? 0.f : 0.5f;
+    for (int c = 0; c < kWideDM; ++c) xl[c * kWave] *= rx;
   }
   const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
   double w_own = 0.0;

