@@ -813,7 +813,7 @@ int size_bucket(int64_t S_pad) {
 int pick_pb(silh_ctx* c, const P2Args& A) {
   if (mfma_pb_max(c->mprec, c->DM) == 1) return 1;
   const int mode = g_tune_mode.load();
-  if (mode == 0) return mfma_pb_default(c->mprec, c->DM);
+  if (mode == 0) return pb_builtin(c->prm.metric, c->mprec, c->DM);
   if (mode == 2 || mode == 3) return mode - 1;
   const std::array<int, 4> key{c->prm.metric, c->mprec, c->DM, size_bucket(c->S_pad)};
   {
@@ -842,7 +842,7 @@ int pick_pb(silh_ctx* c, const P2Args& A) {
     if (ev) (void)hipEventDestroy(ev);
   if (!ok) {
     (void)hipGetLastError();
-    return mfma_pb_default(c->mprec, c->DM);
+    return pb_builtin(c->prm.metric, c->mprec, c->DM);
   }
   const int choice = t2 < t1 ? 2 : 1;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -987,6 +987,11 @@ silh_status validate_params(const silh_params* prm, const float* X, const int32_
 }
 int dm_for(int d) { return phase2_valu_dm(d); }
 silh_status set_error(silh_status st, const char* msg) { return fail(st, "%s", msg); }
+int pb_builtin(int metric, int prec, int DM) {
+  if (metric == SILH_COS && prec == 1 && DM == 32) return 2;
+  return mfma_pb_default(prec, DM);
+}
+
 }  // namespace silh
 
 extern "C" {

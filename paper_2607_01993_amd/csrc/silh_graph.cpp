@@ -222,7 +222,7 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
     if (!launch_pack_mfma(st, metric, g->mprec, DM, b.Y32, b.aux32, b.sp_off, b.cnt, k, b.mu, (int)g->S_cap, b.Ym,
                           b.bnorm))
       return false;
-    if (!launch_phase2_mfma(st, metric, g->mprec, DM, A, b.mu, b.Ym, b.bnorm, mfma_pb_default(g->mprec, DM)))
+    if (!launch_phase2_mfma(st, metric, g->mprec, DM, A, b.mu, b.Ym, b.bnorm, pb_builtin(metric, g->mprec, DM)))
       return false;
   } else if (!launch_phase2_valu(st, metric, DM, A)) {
     return false;

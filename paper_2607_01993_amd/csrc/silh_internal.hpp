@@ -124,6 +124,9 @@ int phase2_mfma_rows(int prec, int DM);
 // 32-element blocks per wave: the default choice, and the launcher (pb 1 or
 // 2; fp8 always runs with 1)
 int mfma_pb_default(int prec, int DM);
+// the built-in block shape with the metric taken into account (cosine bf16
+// at d = 32 measures faster with two blocks per wave, Euclidean with one)
+int pb_builtin(int metric, int prec, int DM);
 int mfma_pb_max(int prec, int DM);
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
                         const void* Ym, const float* bnorm, int pb);
