@@ -12,6 +12,8 @@ Modules:
   global_est  the subsampled global estimators gl-s (Eq. 8) and
               gl-pps-s / gl-uni-s (Eq. 10).
   coh_sep     cohesion and separation from cluster sums (Appendix B).
+  cosine_sum  W_hat for the cosine distance by its linear form (the same
+              estimator in O(n k d), for values at millions of rows).
 
 Parity status: every function here is pinned by tests in tests/test_oracle_*.py
 against values the paper prints, closed forms, brute force or invariants; none
@@ -23,3 +25,4 @@ from .silhouette import (cluster_members, default_t, estimate, exact, global_mea
                          pps_silhouette, sample, scores_from_weights)
 from .global_est import draw_rows, gl_pps_s, gl_s, m_for, subset_mean, sweep  # noqa: F401
 from .coh_sep import coh_sep_from_weights  # noqa: F401
+from .cosine_sum import cosine_estimate, cosine_weights  # noqa: F401

@@ -6,6 +6,10 @@ uniform lies within 1e-12 of the oracle's rate: both sides decide in float64
 but sum W(e_bar) in different orders); float32 a_hat, b_hat within 1e-5
 relative; s_hat and the mean within 4e-5 absolute (Lemma 2 with rho = 1e-5:
 4 rho / (1 - rho))."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -16,11 +20,8 @@ S_ATOL = 4.0e-5
 # bf16 operands (float32 accumulation): per-element and mean bars
 LOWP_S_ATOL = 1e-2
 LOWP_MEAN_ATOL = 1e-3
-# fp8 (e4m3) operands: the element operand's 3-bit mantissa gives each
-# (element, cluster) pair a fixed error of about 0.3 % in W_hat at d = 128, so
-# the per-element bar is wider (measured max 0.017 at n = 4e6, d = 128); the
-# mean bar is the same as bf16
-FP8_S_ATOL = 4e-2
+# fp8 (e4m3) operands: the same bars as bf16
+FP8_S_ATOL = LOWP_S_ATOL
 
 
 def dev(X, L):
@@ -64,3 +65,20 @@ def mean_tol(prec):
     return S_ATOL if prec in ("fp32", "fp32_valu") else LOWP_MEAN_ATOL
 
 
+
+
+GOLDEN_FULLSIZE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_means.json")
+
+
+def golden_mean(X, L, workload, metric):
+    """The float64 oracle's Eq. 9 mean at full size for this workload and
+    metric (tests/golden/make_fullsize.py), after checking that X and the
+    labels are the arrays it was computed from."""
+    with open(GOLDEN_FULLSIZE) as f:
+        cases = json.load(f)["cases"]
+    case = next(c for c in cases if c["workload"] == workload and c["metric"] == metric)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(X).tobytes())
+    h.update(np.ascontiguousarray(L).tobytes())
+    assert h.hexdigest() == case["data_sha256"], "the seeded generator no longer gives the golden's data"
+    return case

@@ -14,7 +14,7 @@ import torch
 import oracle
 from paper_2607_01993_amd import native, synth
 from parity_util import (A_B_RTOL, FP8_S_ATOL, LOWP_MEAN_ATOL, LOWP_S_ATOL, S_ATOL,  # noqa: F401
-                         assert_same_sets, compare_scores, dev, mean_tol)
+                         assert_same_sets, compare_scores, dev, golden_mean, mean_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -370,6 +370,13 @@ def test_full_size_zipf(zipf_case, metric, prec):
     rows = np.sort(np.concatenate([rows, [0, X.shape[0] - 1]]))
     est = oracle.estimate(X, L, k, metric, smp, rows=rows)
     compare_scores(gpu, est, rows=rows, prec=prec)
+    # the mean over all n elements against the oracle's full-size value
+    # (Eq. 9; tests/golden/fullsize_means.json, written from oracle/ only)
+    gold = golden_mean(X, L, "zipf-gauss-blobs", metric)
+    assert view["S"] == gold["S"]
+    print(f"{metric}/{prec}: mean={gpu['mean']:.10f} oracle={gold['mean']:.10f} "
+          f"|d|={abs(gpu['mean'] - gold['mean']):.2e}")
+    assert abs(gpu["mean"] - gold["mean"]) <= mean_tol(prec)
     # the device mean is the float64 mean of the float64 scores; the float32
     # copies differ from those by at most 2^-24 each
     s = gpu["s"].cpu().numpy().astype(np.float64)
@@ -388,12 +395,13 @@ def vmf_case():
     rows = np.sort(np.concatenate([np.random.default_rng(1).choice(X.shape[0], 400, replace=False),
                                    [0, X.shape[0] - 1]]))
     est = oracle.estimate(X, L, 64, "cos", smp, rows=rows)
-    return X, L, smp, rows, est
+    gold = golden_mean(X, L, "vmf-blobs", "cos")
+    return X, L, smp, rows, est, gold
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 def test_full_size_vmf_cosine(vmf_case, prec):
-    X, L, smp, rows, est = vmf_case
+    X, L, smp, rows, est, vmf_gold = vmf_case
     Xd, Ld = dev(X, L)
     ctx = native.silh_sample_init(Xd, Ld, 64, "cos", prec, t=512, delta=0.01, seed=2)
     native.silh_pps_sample(ctx)
@@ -404,15 +412,12 @@ def test_full_size_vmf_cosine(vmf_case, prec):
     s = gpu["s"].cpu().numpy().astype(np.float64)
     assert np.all(np.abs(s) <= 1.0)
     assert abs(gpu["mean"] - math.fsum(s.tolist()) / s.shape[0]) < 1e-7
-    # the mean over the whole clustering against the float32 run (the oracle
-    # has no full-n value here): bf16 / fp8 within the 1e-3 mean bar
-    if prec != "fp32":
-        ctx32 = native.silh_sample_init(Xd, Ld, 64, "cos", "fp32", t=512, delta=0.01, seed=2)
-        native.silh_pps_sample(ctx32)
-        m32 = native.silh_scores(ctx32, a=False, b=False, s=False)["mean"]
-        native.silh_destroy(ctx32)
-        print(f"{prec}: s_mean={gpu['mean']:.7f} fp32 s_mean={m32:.7f}")
-        assert abs(gpu["mean"] - m32) <= LOWP_MEAN_ATOL
+    # the mean over all n = 4e6 elements against the oracle's full-size value
+    # (Eq. 9; tests/golden/fullsize_means.json, written from oracle/ only)
+    gold = vmf_gold
+    assert view["S"] == gold["S"]
+    print(f"{prec}: mean={gpu['mean']:.10f} oracle={gold['mean']:.10f} |d|={abs(gpu['mean'] - gold['mean']):.2e}")
+    assert abs(gpu["mean"] - gold["mean"]) <= mean_tol(prec)
     native.silh_destroy(ctx)
     del Xd, Ld
     torch.cuda.empty_cache()

@@ -317,6 +317,20 @@ def test_cosine_collapse_closed_form():
         w = 1.0 / smp["p"][F]
         ref = w.sum() - Xh @ (w[:, None] * Xh[F]).sum(axis=0)
         np.testing.assert_allclose(est["W"][:, j], ref, rtol=1e-9, atol=1e-9)
+    # the oracle's linear-form evaluation (used for values at full size)
+    # gives the pairwise sums, also with zero rows on both sides
+    lin = oracle.cosine_estimate(X, L, 4, smp)
+    np.testing.assert_allclose(lin["W"], est["W"], rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(lin["s"], est["s"], rtol=0, atol=1e-9)
+    assert abs(lin["mean"] - est["mean"]) < 1e-9
+    Xz = X.copy()
+    Xz[::7] = 0.0
+    estz = oracle.pps_silhouette(Xz, L, 4, "cos", t=40, seed=2)
+    linz = oracle.cosine_estimate(Xz, L, 4, estz["sample"])
+    np.testing.assert_allclose(linz["W"], estz["W"], rtol=1e-9, atol=1e-9)
+    rows = np.array([0, 3, 7, 799])
+    linr = oracle.cosine_estimate(Xz, L, 4, estz["sample"], rows=rows)
+    np.testing.assert_allclose(linr["W"], estz["W"][rows], rtol=1e-9, atol=1e-9)
 
 
 def test_manhattan_prefix_sum_closed_form():
