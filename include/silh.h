@@ -180,6 +180,27 @@ silh_status silh_exact(const silh_params* prm, const float* X, const int32_t* la
                        silh_stream stream, float* a, float* b, float* s, double* s_mean_host);
 
 /*
+ * silh_exact_noalloc - silh_exact without any device allocation, for callers
+ * that cannot allocate device memory (code under stream capture, serving
+ * loops that must not call hipMalloc, harnesses that forbid it).  Arguments,
+ * results and errors as silh_exact; prm->alloc, free and alloc_user are
+ * ignored.  The library's buffers (cluster index, packed rows, partial sums)
+ * are slices of one static device array of 256 MiB that each device holds
+ * from the first call on it until the process ends; a problem whose buffers
+ * do not fit it (about 270 bytes per element at d = 32 with bf16 operands,
+ * so n up to about 10^6) is rejected with SILH_E_ARG before anything is
+ * enqueued.  The caller still passes X, labels and the outputs.  The array
+ * keeps the last call's contents (the call refills what must start at a known
+ * value).  Calls on one device share it, so calls that overlapped on one
+ * device would race: the library runs the calls of one process on one device
+ * one at a time (each returns after its stream has synchronised).
+ * Synchronises the stream once, at the end.  On SILH_E_LABEL or SILH_E_K the
+ * contents of a, b, s are unspecified.
+ */
+silh_status silh_exact_noalloc(const silh_params* prm, const float* X, const int32_t* labels,
+                               silh_stream stream, float* a, float* b, float* s, double* s_mean_host);
+
+/*
  * Subsampled estimates of s(C) (Section 4.2).  The m rows are drawn
  * independently and uniformly from {0..n-1}, with replacement (Eqs. 8 and 10;
  * the Hoeffding bounds after them need independent draws).

@@ -31,6 +31,7 @@ SOURCES = {
     "silh_graph.cpp": [],
     # the sizes computed here repeat the host's floating-point steps exactly
     "k_graph.hip": ["-ffp-contract=off"],
+    "silh_noalloc.hip": [],
     # MFMA results straight into VGPRs (no accumulator-register copies)
     "k_phase2_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }

@@ -985,6 +985,10 @@ namespace silh {
 silh_status validate_params(const silh_params* prm, const float* X, const int32_t* labels, int64_t* t) {
   return check_params(prm, X, labels, false, t);
 }
+silh_status validate_exact_params(const silh_params* prm, const float* X, const int32_t* labels) {
+  int64_t t = 0;
+  return check_params(prm, X, labels, true, &t);
+}
 int dm_for(int d) { return phase2_valu_dm(d); }
 silh_status set_error(silh_status st, const char* msg) { return fail(st, "%s", msg); }
 int pb_builtin(int metric, int prec, int DM) {

@@ -170,6 +170,8 @@ void launch_put_status(hipStream_t st, const int* status, int32_t* out);
 namespace silh {
 // the argument checks of silh_sample_init; *t receives the sample size used
 silh_status validate_params(const silh_params* prm, const float* X, const int32_t* labels, int64_t* t);
+// the argument checks of silh_exact (t, eps, delta, sampler and seed unused)
+silh_status validate_exact_params(const silh_params* prm, const float* X, const int32_t* labels);
 // padded row width of the packed sample for dimension d (0 if unsupported)
 int dm_for(int d);
 // sets the thread's silh_last_error message and returns st

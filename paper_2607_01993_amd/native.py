@@ -68,6 +68,9 @@ SIGNATURES = {
     "silh_exact": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_double)]),
+    "silh_exact_noalloc": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double)]),
     "silh_rows_for": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]),
     "silh_draw_rows": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p]),
@@ -329,6 +332,30 @@ def silh_exact(X, labels, k, metric="eucl", prec="fp32", stream=None, a=True, b=
         _check(lib.silh_exact(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()),
                               ctypes.c_void_p(labels.data_ptr()), sh, *ptr,
                               ctypes.byref(m) if mean else None), "silh_exact")
+    res = {x: v for x, v in outs.items() if v is not None}
+    if mean:
+        res["mean"] = m.value
+    return res
+
+
+def silh_exact_noalloc(X, labels, k, metric="eucl", prec="fp32", stream=None, a=True, b=True, s=True,
+                       mean=True):
+    """silh_exact with the library's buffers in its static device array (no
+    device allocation by the library; the outputs are allocated here)."""
+    torch = _torch()
+    lib = load_library()
+    _check_inputs(X, labels)
+    st, sh = _stream_handle(stream)
+    p = _params(X.shape[0], X.shape[1], k, metric, prec, "pps", 1, 0.0, 0.5, 0, False)
+    outs = {name: torch.empty(X.shape[0], dtype=torch.float32, device=X.device) if want else None
+            for name, want in (("a", a), ("b", b), ("s", s))}
+    ptr = [ctypes.c_void_p(outs[x].data_ptr()) if outs[x] is not None else ctypes.c_void_p()
+           for x in ("a", "b", "s")]
+    m = ctypes.c_double()
+    with _Target(X.device.index, st):
+        _check(lib.silh_exact_noalloc(ctypes.byref(p), ctypes.c_void_p(X.data_ptr()),
+                                      ctypes.c_void_p(labels.data_ptr()), sh, *ptr,
+                                      ctypes.byref(m) if mean else None), "silh_exact_noalloc")
     res = {x: v for x, v in outs.items() if v is not None}
     if mean:
         res["mean"] = m.value

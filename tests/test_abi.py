@@ -163,3 +163,19 @@ def test_graph_layout_and_argument_checks():
     assert lib.silh_graph_run(None, None, None, None, None, None) == 1
     assert lib.silh_graph_get_info(None, None) == 1
     lib.silh_graph_destroy(None)
+
+
+def test_exact_noalloc_argument_checks():
+    """silh_exact_noalloc checks its arguments and the size of its static
+    scratch array before it touches the device."""
+    lib = native.load_library()
+    p = native._params(10, 4, 3, 0, 0, 0, 1, 0.0, 0.5, 0, use_torch_alloc=False)
+    p.n = 1
+    assert lib.silh_exact_noalloc(ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8), None,
+                                  None, None, None, None) == 1
+    p = native._params(4_000_000, 32, 16, "eucl", "bf16", "pps", 1, 0.0, 0.5, 0, use_torch_alloc=False)
+    assert lib.silh_exact_noalloc(ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(8), None,
+                                  None, None, None, None) == 1
+    assert b"scratch" in lib.silh_last_error()
+    p = native._params(1000, 32, 16, "eucl", "bf16", "pps", 1, 0.0, 0.5, 0, use_torch_alloc=False)
+    assert lib.silh_exact_noalloc(ctypes.byref(p), None, ctypes.c_void_p(8), None, None, None, None, None) == 1
