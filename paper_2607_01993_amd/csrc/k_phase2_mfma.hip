@@ -55,6 +55,21 @@ constexpr float kFp8Scale = 64.0f;
 
 constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
 
+// Euclidean pairs prone to cancellation in the expanded form: with x~, y~
+// centred on mu_j, the squared distance c = |x~|^2 + |y~|^2 - 2 x~.y~ carries
+// an absolute error of order eps (|x~|^2 + |y~|^2), so a pair with
+// c < tau (|x~|^2 + |y~|^2) loses more than eps/tau of its relative accuracy
+// (and the square root halves that).  Such a pair has |x~| < 2|y~| when
+// tau < 0.2 (else c >= (|x~| - |y~|)^2 >= |x~|^2/4), hence c < 5 tau |y~|^2:
+// every pair with c below 6 tau |y~|^2 (a margin for the error of c itself)
+// is evaluated again as sum (x - y)^2 from the float32 rows, which has no
+// cancellation.  tau = 2^-5 for float32 operands (relative error of d below
+// 2^-17 for the others) and 2^-8 for bf16 (whose own rounding of x~ and y~
+// dominates below that).  The self pair d(e, e) is one of them and comes out
+// exactly 0.
+template <int P>
+constexpr float kRecomputeThr = P == 0 ? 6.0f / 32.0f : 6.0f / 256.0f;
+
 constexpr int kCenterRows = 256;
 
 __host__ __device__ constexpr int round_up_c(int a, int b) { return (a + b - 1) / b * b; }
@@ -182,6 +197,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
     for (int c = 0; c < C::KP; c += 4) out[c / 4] = fp8_pack4(row[c], row[c + 1], row[c + 2], row[c + 3]);
     return;
   }
+  float thr = 0.0f;
   if (real) {
     const float* y = Y32 + (size_t)s * DM;
     const float* m = mu + (size_t)j * C::KP;
@@ -194,6 +210,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       row[c] = -2.0f * alpha * v;
     }
     const float bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
+    thr = M == kEucl ? kRecomputeThr<P> * ny : 0.0f;
     if (P == 0) {
       row[DM] = 1.0f;
       row[DM + 1] = bn;
@@ -202,6 +219,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       split3(bn, row[DM + 3], row[DM + 4], row[DM + 5]);
     }
   }
+  bnorm[s] = thr;
   if constexpr (P == 0) {
     float* out = (float*)Ym + (size_t)s * C::KP;
 #pragma unroll
@@ -329,9 +347,9 @@ __device__ __forceinline__ void load_chunk(const float* __restrict__ xp, int c, 
   }
 }
 
-// one tile's B operand (this lane's half row), weight and element id (the
-// fp8 path loads the sample's norm term instead of the id)
-template <int P, int DM>
+// one tile's B operand (this lane's half row), weight and the sample's
+// value in bnorm (fp8: its norm term; Euclidean: its recompute threshold)
+template <int M, int P, int DM>
 __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const float* __restrict__ w,
                                           const int32_t* __restrict__ gid_pk,
                                           const float* __restrict__ bnorm, int row0, uint32_t lane_off,
@@ -343,7 +361,7 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
   const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)row0 * (size_t)(C::KP * C::ELEM),
                           32 * C::KP * C::ELEM);
   const auto rw = rsrc_at(w + row0, 32 * 4);
-  const auto rg = rsrc_at(P == 2 ? (const void*)(bnorm + row0) : (const void*)(gid_pk + row0), 32 * 4);
+  const auto rg = rsrc_at(bnorm + row0, 32 * 4);
   if constexpr (P == 2) {
 #pragma unroll
     for (int s = 0; s < C::NSTEP; ++s) {
@@ -361,17 +379,24 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
       b.v[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 16u * s, 0, 0));
   }
   wj = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * col, 0, 0));
-  gj = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0);
+  gj = (P == 2 || M == kEucl) ? (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0) : 0;
 }
 
+// waves per SIMD each shape must keep (the register count of the shape
+// without the recompute path, which must not take more)
 template <int M, int P, int DM, int PB>
-__global__ __launch_bounds__(256) void k_p2_mfma(
+constexpr int kMinWaves = M != kEucl ? 1 : (PB == 2 ? (DM <= 16 ? 3 : (DM <= 32 ? 2 : 1))
+                                             : (DM <= 16 ? 4 : (DM <= 32 ? 4 : (DM <= 64 ? 3 : (DM <= 128 ? 2 : 1)))));
+
+template <int M, int P, int DM, int PB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma(
     const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
     const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt,
     const int32_t* __restrict__ csize, int k, const float* __restrict__ mu,
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
-    float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm) {
+    float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm,
+    const float* __restrict__ Y32, int DMY) {
   using C = MCfg<P, DM>;
   // the augmentation columns always fall in the upper half of the row
   constexpr int AUG0 = DM - C::HALF;
@@ -554,7 +579,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
     int g = 0;
     // one tile: getB(q) gives step q of this lane's B fragment (a float2 of
     // two steps for float32), from registers or read from LDS just in time
-    auto tile = [&](auto&& getB, float wj, int gj, bool last) {
+    auto tile = [&](auto&& getB, float wj, int gj, int srow, bool last) {
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
         f32x16 c;
@@ -583,17 +608,32 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
           for (int s = 0; s < C::NSTEP; ++s)
             c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], getB(s), c, 0, 0, 0, 0, 0, 0);
         }
-        if (M == kEucl) {
-          // d(e, e) = 0 exactly: the expanded form leaves rounding noise
-          // there, which the square root would amplify.  Only a column that
-          // holds one of this block's own 32 elements (in this lane's half)
-          // is touched.
-          const int self = gj - (P0 + 32 * b);
-          if ((unsigned)self < 32u && ((self >> 2) & 1) == h) {
-            const int rh = ((self >> 3) << 2) | (self & 3);
+        if constexpr (M == kEucl) {
+          // pairs prone to cancellation (kRecomputeThr) get their squared
+          // distance again from the float32 rows; rare outside the self pair
+          const float thr = __int_as_float(gj);
+          float mn = c[0];
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-              if (r == rh) c[r] = 0.0f;
+          for (int r = 1; r < 16; ++r) mn = fminf(mn, c[r]);
+          if (__builtin_expect(mn < thr, 0)) {
+            // one code copy for the flagged rows, taken in turn
+            unsigned flagged = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) flagged |= (c[r] < thr ? 1u : 0u) << r;
+            const float* yr = Y32 + (size_t)(srow + col) * DMY;
+            while (flagged) {
+              const int r = __builtin_ctz(flagged);
+              flagged &= flagged - 1;
+              const int e = P0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3);
+              const float* xp = X + (size_t)(e < n ? e : n - 1) * d;
+              float acc2 = 0.0f;
+              for (int q = 0; q < d; ++q) {
+                const float t = xp[q] - yr[q];
+                acc2 = fmaf(t, t, acc2);
+              }
+#pragma unroll
+              for (int q = 0; q < 16; ++q) c[q] = q == r ? acc2 : c[q];
+            }
           }
         }
         const float wt = P == 2 ? wj * (1.0f / S2) : wj;
@@ -635,7 +675,7 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
           }
           if (threadIdx.x < 32) {
             sw[tt] = w[r0 + threadIdx.x];
-            sg[tt] = P == 2 ? __float_as_int(bnorm[r0 + threadIdx.x]) : gid_pk[r0 + threadIdx.x];
+            sg[tt] = (P == 2 || M == kEucl) ? __float_as_int(bnorm[r0 + threadIdx.x]) : 0;
           }
         }
       };
@@ -682,7 +722,8 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
                 return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
               }
             };
-            tile(fromLds, ldsW[buf][32 * tt + col], ldsG[buf][32 * tt + col], t + tt + 1 == ntile);
+            tile(fromLds, ldsW[buf][32 * tt + col], ldsG[buf][32 * tt + col], base + (t + tt) * 32,
+                 t + tt + 1 == ntile);
           }
         }
         store(buf ^ 1);
@@ -695,19 +736,19 @@ __global__ __launch_bounds__(256) void k_p2_mfma(
       // each tile covers only that tile's loads; an odd last tile runs after
       // the loop from the buffer already loaded, and its successor is loaded
       // into the same buffer once its MFMAs are issued.
-      if (ntile > 0 && pre != base) load_tile<P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
+      if (ntile > 0 && pre != base) load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
       int t = 0;
       for (; t + 2 <= ntile; t += 2) {
-        load_tile<P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
-        tile([&](int q) { return b0.v[q]; }, w0, g0, false);
+        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
+        tile([&](int q) { return b0.v[q]; }, w0, g0, base + t * 32, false);
         pre = clamp_row(base + (t + 2) * 32);
-        load_tile<P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
-        tile([&](int q) { return b1.v[q]; }, w1, g1, t + 2 == ntile);
+        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
+        tile([&](int q) { return b1.v[q]; }, w1, g1, base + (t + 1) * 32, t + 2 == ntile);
       }
       if (t < ntile) {
-        tile([&](int q) { return b0.v[q]; }, w0, g0, true);
+        tile([&](int q) { return b0.v[q]; }, w0, g0, base + t * 32, true);
         pre = clamp_row(base + ntile * 32);
-        load_tile<P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
+        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
       }
     }
     const int sz = csize[j];
@@ -764,7 +805,7 @@ static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, con
   const int blocks = (int)ceil_div(A.n, 128 * PB);
   hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
                      A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart,
-                     bnorm);
+                     bnorm, A.Y, DM);
 }
 
 template <int M, int P, int DM>

@@ -149,6 +149,40 @@ def tiny_case(n: int, d: int, k: int, seed: int, sigma=(0.5, 2.0), sizes=None):
     return gaussian_blobs(n, d, k, seed=seed, sizes=sizes, sigma=sigma)
 
 
+def split_blobs(n: int, d: int, k: int, seed: int, sep: float = 100.0, tight: float = 0.01,
+                offset: float = 1000.0, dup: float = 0.0):
+    """Cluster 0 is two tight blobs (sigma = `tight`) `sep` apart, so its
+    centre lies far from every one of its points while their near neighbours
+    are close; clusters 1..k-1 are ordinary blobs (sigma 1) around centres
+    U[-sep, sep]^d.  Everything is shifted by `offset` in every coordinate.
+    With dup > 0 every second row of cluster 0 is a copy of the row before it
+    moved by N(0, dup^2) per coordinate (near-duplicate pairs).  Rows are
+    shuffled; half the rows belong to cluster 0."""
+    rng = np.random.default_rng(seed)
+    n0 = n // 2
+    rest = n - n0
+    sizes = np.full(k - 1, rest // (k - 1))
+    sizes[0] += rest - int(sizes.sum())
+    c0 = rng.uniform(-sep, sep, size=d)
+    direc = rng.standard_normal(d)
+    direc /= np.linalg.norm(direc)
+    half = n0 // 2
+    A = c0 + rng.normal(scale=tight, size=(half, d))
+    B = c0 + sep * direc + rng.normal(scale=tight, size=(n0 - half, d))
+    X0 = np.concatenate([A, B])
+    if dup > 0.0:
+        X0[1::2] = X0[0:-1:2][: X0[1::2].shape[0]] + rng.normal(scale=dup, size=X0[1::2].shape)
+    parts = [X0]
+    labels = [np.zeros(n0, dtype=np.int32)]
+    for j in range(1, k):
+        cj = rng.uniform(-sep, sep, size=d)
+        parts.append(cj + rng.normal(size=(int(sizes[j - 1]), d)))
+        labels.append(np.full(int(sizes[j - 1]), j, dtype=np.int32))
+    X = (np.concatenate(parts) + offset).astype(np.float32)
+    L = np.concatenate(labels)
+    return _shuffle(rng, X, L)
+
+
 # ---------------------------------------------------------------------------
 # Exponential blobs and Voronoi clusterings (the k-sweep workload), and the
 # serving workload's dataset pool and request stream.
