@@ -558,7 +558,8 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
                                               const float* __restrict__ X, int d, int DM,
                                               const double* __restrict__ p_gid,
                                               const int32_t* __restrict__ s_off,
-                                              const int32_t* __restrict__ sp_off, int mode, int cap,
+                                              const int32_t* __restrict__ sp_off, int mode,
+                                              const float* __restrict__ rn, int cap,
                                               int64_t* __restrict__ gid_view,
                                               int32_t* __restrict__ gid_pk, float* __restrict__ w32,
                                               float* __restrict__ aux32, float* __restrict__ Y32) {
@@ -575,41 +576,59 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
   const float* xr = X + (size_t)g * d;
   float* yr = Y32 + (size_t)dst * DM;
   const bool vec = (d & 3) == 0 && ((uintptr_t)X & 15) == 0;
-  double scale = 1.0;
+  // cosine: the row times its float32 reciprocal norm, the same product the
+  // Phase-2 kernels form for the element side (identical rows stay identical)
+  float scale = 1.0f;
   if (mode == 1) {
-    double s2 = 0.0;
-    if (vec) {
-      for (int c = 0; c < d; c += 4) {
-        const float4 v = *(const float4*)(xr + c);
-        s2 = s2 + (double)v.x * (double)v.x;
-        s2 = s2 + (double)v.y * (double)v.y;
-        s2 = s2 + (double)v.z * (double)v.z;
-        s2 = s2 + (double)v.w * (double)v.w;
-      }
-    } else {
-      for (int c = 0; c < d; ++c) s2 = s2 + (double)xr[c] * (double)xr[c];
-    }
-    scale = s2 > 0.0 ? 1.0 / __dsqrt_rn(s2) : 0.0;
-    aux32[dst] = s2 > 0.0 ? 0.0f : 0.5f;
+    scale = rn[g];
+    aux32[dst] = scale > 0.0f ? 0.0f : 0.5f;
   }
   if (vec) {
     // 16-byte row chunks (DM is a multiple of 8)
     for (int c = 0; c < DM; c += 4) {
       const float4 v = c < d ? *(const float4*)(xr + c) : float4{0.f, 0.f, 0.f, 0.f};
-      *(float4*)(yr + c) = float4{(float)((double)v.x * scale), (float)((double)v.y * scale),
-                                  (float)((double)v.z * scale), (float)((double)v.w * scale)};
+      *(float4*)(yr + c) = float4{v.x * scale, v.y * scale, v.z * scale, v.w * scale};
     }
   } else {
-    for (int c = 0; c < DM; ++c) yr[c] = c < d ? (float)((double)xr[c] * scale) : 0.0f;
+    for (int c = 0; c < DM; ++c) yr[c] = c < d ? xr[c] * scale : 0.0f;
   }
+}
+
+// Reciprocal L2 norm of every row in float32 (one rounding per operation:
+// a fused multiply-add chain in coordinate order, then a correctly rounded
+// square root and division), 0 for a zero row.  The cosine kernels scale both
+// the element rows and the packed sample rows by it.
+__global__ __launch_bounds__(256) void k_rnorm(const float* __restrict__ X, int n, int d, float* __restrict__ rn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* xr = X + (size_t)i * d;
+  float s2 = 0.0f;
+  if ((d & 3) == 0 && ((uintptr_t)X & 15) == 0) {
+    for (int c = 0; c < d; c += 4) {
+      const float4 v = *(const float4*)(xr + c);
+      s2 = fmaf(v.x, v.x, s2);
+      s2 = fmaf(v.y, v.y, s2);
+      s2 = fmaf(v.z, v.z, s2);
+      s2 = fmaf(v.w, v.w, s2);
+    }
+  } else {
+    for (int c = 0; c < d; ++c) s2 = fmaf(xr[c], xr[c], s2);
+  }
+  rn[i] = s2 > 0.0f ? 1.0f / sqrtf(s2) : 0.0f;
+}
+
+void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_rnorm, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, X, n, d, rn);
 }
 
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
                  const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
-                 const int32_t* s_off, const int32_t* sp_off, int mode, int cap, int64_t* gid_view,
+                 const int32_t* s_off, const int32_t* sp_off, int mode, const float* rn, int cap,
+                 int64_t* gid_view,
                  int32_t* gid_pk, float* w32, float* aux32, float* Y32) {
   hipLaunchKernelGGL(k_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos, n,
-                     X, d, DM, p_gid, s_off, sp_off, mode, cap, gid_view, gid_pk, w32, aux32, Y32);
+                     X, d, DM, p_gid, s_off, sp_off, mode, rn, cap, gid_view, gid_pk, w32, aux32, Y32);
 }
 
 // ----------------------------------------------------------------------------

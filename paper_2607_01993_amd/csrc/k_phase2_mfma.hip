@@ -55,8 +55,8 @@ constexpr float kFp8Scale = 64.0f;
 
 constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
 
-// Euclidean pairs prone to cancellation in the expanded form: with x~, y~
-// centred on mu_j, the squared distance c = |x~|^2 + |y~|^2 - 2 x~.y~ carries
+// Pairs prone to cancellation in the expanded form: with x~, y~ centred on
+// mu_j, the squared distance c = |x~|^2 + |y~|^2 - 2 x~.y~ carries
 // an absolute error of order eps (|x~|^2 + |y~|^2), so a pair with
 // c < tau (|x~|^2 + |y~|^2) loses more than eps/tau of its relative accuracy
 // (and the square root halves that).  Such a pair has |x~| < 2|y~| when
@@ -66,7 +66,9 @@ constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
 // cancellation.  tau = 2^-5 for float32 operands (relative error of d below
 // 2^-17 for the others) and 2^-8 for bf16 (whose own rounding of x~ and y~
 // dominates below that).  The self pair d(e, e) is one of them and comes out
-// exactly 0.
+// exactly 0.  Cosine (unit rows, c scaled by 1/2) takes the same test; its
+// rows are the element's row times its reciprocal norm, the same product as
+// the packed sample row, so the self pair is exactly 0 there too.
 template <int P>
 constexpr float kRecomputeThr = P == 0 ? 6.0f / 32.0f : 6.0f / 256.0f;
 
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       row[c] = -2.0f * alpha * v;
     }
     const float bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
-    thr = M == kEucl ? kRecomputeThr<P> * ny : 0.0f;
+    thr = kRecomputeThr<P> * alpha * ny;
     if (P == 0) {
       row[DM] = 1.0f;
       row[DM + 1] = bn;
@@ -379,24 +381,26 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
       b.v[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 16u * s, 0, 0));
   }
   wj = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * col, 0, 0));
-  gj = (P == 2 || M == kEucl) ? (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0) : 0;
+  gj = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0);
 }
 
-// waves per SIMD each shape must keep (the register count of the shape
-// without the recompute path, which must not take more)
+// waves per SIMD the one-block shapes from d = 32 on keep (their occupancy
+// without the recompute path, which must not lower it)
 template <int M, int P, int DM, int PB>
-constexpr int kMinWaves = M != kEucl ? 1 : (PB == 2 ? (DM <= 16 ? 3 : (DM <= 32 ? 2 : 1))
-                                             : (DM <= 16 ? 4 : (DM <= 32 ? 4 : (DM <= 64 ? 3 : (DM <= 128 ? 2 : 1)))));
+constexpr int kMinWaves = (P == 2 || PB == 2 || DM < 32) ? 1 : DM == 32 ? (P == 1 ? 4 : 1) : DM == 64 ? 3 : DM == 128 ? 2 : 1;
 
+// One block of the Phase-2 launch: 4 waves x PB x 32 elements, from element
+// blk * 128 * PB on.  The kernels below run it for blockIdx.x (one request)
+// or for the (request, block) work items of a multi-request launch.
 template <int M, int P, int DM, int PB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma(
-    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+__device__ __forceinline__ void p2_mfma_block(
+    const int blk, const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
     const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt,
     const int32_t* __restrict__ csize, int k, const float* __restrict__ mu,
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
     float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm,
-    const float* __restrict__ Y32, int DMY) {
+    const float* __restrict__ Y32, int DMY, const float* __restrict__ aux, const float* __restrict__ rn) {
   using C = MCfg<P, DM>;
   // the augmentation columns always fall in the upper half of the row
   constexpr int AUG0 = DM - C::HALF;
@@ -426,7 +430,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
   const int h = lane >> 5;
   const int col = lane & 31;
   // PB blocks of 32 elements per wave share every B tile
-  const int P0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 * PB);
+  const int P0 = __builtin_amdgcn_readfirstlane((blk * 4 + (threadIdx.x >> 6)) * 32 * PB);
   const float alpha = M == kCos ? 0.5f : 1.0f;
   const uint32_t lane_off = (uint32_t)((col * C::KP + h * C::HALF) * C::ELEM);  // bytes
   // the element whose sums this lane ends up holding (twice: lanes l, l^1)
@@ -450,22 +454,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
     const int pb = P0 + 32 * b + col;
     const int pa = pb < n ? pb : n - 1;
     const float* xp = X + (size_t)pa * d;
-    float p = 0.f;
 #pragma unroll
     for (int i0 = 0; i0 < C::HALF; i0 += V) {
       float xc[V];
       load_chunk<V>(xp, h * C::HALF + i0, d, vec, xc);
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        xr[b][i0 + e] = xc[e];
-        p = fmaf(xc[e], xc[e], p);
-      }
+      for (int e = 0; e < V; ++e) xr[b][i0 + e] = xc[e];
     }
     ux[b] = 0.f;
     if (M == kCos) {
-      const float s2 = p + __shfl_xor(p, 32, kWave);
-      const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
-      ux[b] = s2 > 0.f ? 0.f : 0.5f;
+      // unit vector: the row times its float32 reciprocal norm, the product
+      // the packing forms for the sample rows (u = 0.5 for a zero row)
+      const float rx = rn[pa];
+      ux[b] = rx > 0.f ? 0.f : 0.5f;
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
     }
@@ -608,7 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
           for (int s = 0; s < C::NSTEP; ++s)
             c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], getB(s), c, 0, 0, 0, 0, 0, 0);
         }
-        if constexpr (M == kEucl) {
+        if constexpr (P != 2) {
           // pairs prone to cancellation (kRecomputeThr) get their squared
           // distance again from the float32 rows; rare outside the self pair
           const float thr = __int_as_float(gj);
@@ -624,12 +625,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
             while (flagged) {
               const int r = __builtin_ctz(flagged);
               flagged &= flagged - 1;
-              const int e = P0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3);
-              const float* xp = X + (size_t)(e < n ? e : n - 1) * d;
+              const int e0 = P0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3);
+              const int e = e0 < n ? e0 : n - 1;
+              const float* xp = X + (size_t)e * d;
               float acc2 = 0.0f;
-              for (int q = 0; q < d; ++q) {
-                const float t = xp[q] - yr[q];
-                acc2 = fmaf(t, t, acc2);
+              if constexpr (M == kEucl) {
+                for (int q = 0; q < d; ++q) {
+                  const float t = xp[q] - yr[q];
+                  acc2 = fmaf(t, t, acc2);
+                }
+              } else {
+                // cosine: half the squared distance of the unit rows, plus u
+                const float rx = rn[e];
+                for (int q = 0; q < d; ++q) {
+                  const float t = xp[q] * rx - yr[q];
+                  acc2 = fmaf(t, t, acc2);
+                }
+                acc2 = fmaf(0.5f, acc2, (rx > 0.f ? 0.f : 0.5f) + aux[srow + col]);
               }
 #pragma unroll
               for (int q = 0; q < 16; ++q) c[q] = q == r ? acc2 : c[q];
@@ -675,7 +687,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
           }
           if (threadIdx.x < 32) {
             sw[tt] = w[r0 + threadIdx.x];
-            sg[tt] = (P == 2 || M == kEucl) ? __float_as_int(bnorm[r0 + threadIdx.x]) : 0;
+            sg[tt] = __float_as_int(bnorm[r0 + threadIdx.x]);
           }
         }
       };
@@ -785,10 +797,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
   __syncthreads();
   if (threadIdx.x < PB) {
     const int g = threadIdx.x;
-    const int row0 = blockIdx.x * 128 * PB + 128 * g;
+    const int row0 = blk * 128 * PB + 128 * g;
     const double v = ((sh32[4 * g] + sh32[4 * g + 1]) + sh32[4 * g + 2]) + sh32[4 * g + 3];
     if (row0 < n) bpart[row0 >> 7] = v;
   }
+}
+
+template <int M, int P, int DM, int PB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma(
+    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+    const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
+    const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt,
+    const int32_t* __restrict__ csize, int k, const float* __restrict__ mu,
+    float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
+    float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm,
+    const float* __restrict__ Y32, int DMY, const float* __restrict__ aux, const float* __restrict__ rn) {
+  p2_mfma_block<M, P, DM, PB>(blockIdx.x, X, n, d, labels, Ym, w, gid_pk, sp_off, cnt, csize, k, mu, a_out, b_out,
+                              s_out, What, bpart, bnorm, Y32, DMY, aux, rn);
+}
+
+// Several requests in one launch: workgroup i runs work item i = (request,
+// block), doing exactly what that block of the request's own launch does, so
+// results do not depend on which requests share the launch.  The hardware
+// dispatcher hands the workgroups to the CUs in order as slots free up, which
+// is the schedule a software work queue would give; a loop over items inside
+// one workgroup kept the block's state across iterations and spilled 15-47
+// registers in the shapes from d = 32 on.  The job table and the items are
+// read through the constant address space, so their values sit in scalar
+// registers like kernel arguments.
+template <int M, int P, int DM, int PB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma_jobs(
+    const P2Job* __restrict__ jobs, const int2* __restrict__ items) {
+  typedef const __attribute__((address_space(4))) P2Job* cjob_ptr;
+  typedef const __attribute__((address_space(4))) int* citem_ptr;
+  const int jx = ((citem_ptr)items)[2 * blockIdx.x];
+  const int blk = ((citem_ptr)items)[2 * blockIdx.x + 1];
+  const auto& J = ((cjob_ptr)jobs)[jx];
+  p2_mfma_block<M, P, DM, PB>(blk, J.X, J.n, J.d, J.labels, J.Ym, J.w, J.gid_pk, J.sp_off, J.cnt, J.csize, J.k, J.mu,
+                              J.a, J.b, J.s, J.What, J.bpart, J.bnorm, J.Y32, DM, J.aux, J.rn);
 }
 
 // 32-element blocks per wave (PB): two halve the B-operand loads per pair
@@ -805,7 +851,7 @@ static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, con
   const int blocks = (int)ceil_div(A.n, 128 * PB);
   hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
                      A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart,
-                     bnorm, A.Y, DM);
+                     bnorm, A.Y, DM, A.aux, A.rn);
 }
 
 template <int M, int P, int DM>
@@ -818,6 +864,17 @@ static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, co
     }
   }
   launch_mfma_pb<M, P, DM, 1>(st, A, mu, Ym, bnorm);
+}
+
+template <int M, int P, int DM>
+static void launch_jobs_one(hipStream_t st, const P2Job* jobs, const int2* items, int nitems, int pb) {
+  if constexpr (P != 2 && DM <= 64) {
+    if (pb == 2) {
+      hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 2>), dim3(nitems), dim3(256), 0, st, jobs, items);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 1>), dim3(nitems), dim3(256), 0, st, jobs, items);
 }
 
 template <int M, int P, int DM>
@@ -886,6 +943,12 @@ bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float*
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
                         const void* Ym, const float* bnorm, int pb) {
   SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym, bnorm, pb);
+}
+
+bool launch_phase2_mfma_jobs(hipStream_t st, int metric, int prec, int DM, int pb, const P2Job* jobs,
+                             const int2* items, int nitems) {
+  if (nitems <= 0) return true;
+  SILH_MFMA_DISPATCH(launch_jobs_one, st, jobs, items, nitems, pb);
 }
 
 int phase2_mfma_rows(int, int) { return 128; }

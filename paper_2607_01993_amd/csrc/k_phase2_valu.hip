@@ -68,17 +68,17 @@ __device__ __forceinline__ float dist32_col(const float* __restrict__ x, const f
 // half (c0 = 128), adds Wpart and finishes.  ystride is the packed sample's
 // row length.
 template <int M, int DM, int PASS>
-__global__ __launch_bounds__(kP2Rows) void k_p2_valu(
-    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+__device__ __forceinline__ void p2_valu_block(
+    const int blk, const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const float* __restrict__ Y, const float* __restrict__ w, const float* __restrict__ aux,
     const int32_t* __restrict__ sp_off,
     const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
     float* __restrict__ What, double* __restrict__ bpart, int c0, int ystride,
-    double* __restrict__ Wpart) {
+    double* __restrict__ Wpart, const float* __restrict__ rn) {
   static_assert(PASS == 0 || M == kManh || M == kCanb, "only sums over coordinates split");
   __shared__ double sh[kP2Rows / kWave];
-  const int e = blockIdx.x * kP2Rows + threadIdx.x;
+  const int e = blk * kP2Rows + threadIdx.x;
   const bool valid = e < n;
   const int er = valid ? e : n - 1;
 
@@ -87,12 +87,9 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
 #pragma unroll
   for (int c = 0; c < DM; ++c) x[c] = c0 + c < d ? xr[c] : 0.0f;
   float ux = 0.f;
-  if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
-    float s2 = 0.f;
-#pragma unroll
-    for (int c = 0; c < DM; ++c) s2 = fmaf(x[c], x[c], s2);
-    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
-    ux = s2 > 0.f ? 0.f : 0.5f;
+  if (M == kCos) {  // unit vector: the row times its reciprocal norm (zero stays zero, u = 0.5)
+    const float rx = rn[er];
+    ux = rx > 0.f ? 0.f : 0.5f;
 #pragma unroll
     for (int c = 0; c < DM; ++c) x[c] *= rx;
   }
@@ -140,7 +137,35 @@ __global__ __launch_bounds__(kP2Rows) void k_p2_valu(
     if (s_out) s_out[e] = (float)s;
   }
   const double tot = block_sum_f64<kP2Rows>(valid ? s : 0.0, sh);
-  if (threadIdx.x == 0) bpart[blockIdx.x] = tot;
+  if (threadIdx.x == 0) bpart[blk] = tot;
+}
+
+template <int M, int DM, int PASS>
+__global__ __launch_bounds__(kP2Rows) void k_p2_valu(
+    const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
+    const float* __restrict__ Y, const float* __restrict__ w, const float* __restrict__ aux,
+    const int32_t* __restrict__ sp_off,
+    const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
+    float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
+    float* __restrict__ What, double* __restrict__ bpart, int c0, int ystride,
+    double* __restrict__ Wpart, const float* __restrict__ rn) {
+  p2_valu_block<M, DM, PASS>(blockIdx.x, X, n, d, labels, Y, w, aux, sp_off, cnt, csize, k, a_out, b_out, s_out,
+                             What, bpart, c0, ystride, Wpart, rn);
+}
+
+// Several requests in one launch (one-pass shapes): workgroup i runs work
+// item i = (request, block), exactly as that block of the request's own
+// launch; job table and items read through the constant address space.
+template <int M, int DM>
+__global__ __launch_bounds__(kP2Rows) void k_p2_valu_jobs(const P2Job* __restrict__ jobs,
+                                                          const int2* __restrict__ items) {
+  typedef const __attribute__((address_space(4))) P2Job* cjob_ptr;
+  typedef const __attribute__((address_space(4))) int* citem_ptr;
+  const int jx = ((citem_ptr)items)[2 * blockIdx.x];
+  const int blk = ((citem_ptr)items)[2 * blockIdx.x + 1];
+  const auto& J = ((cjob_ptr)jobs)[jx];
+  p2_valu_block<M, DM, 0>(blk, J.X, J.n, J.d, J.labels, J.Y32, J.w, J.aux, J.sp_off, J.cnt, J.csize, J.k, J.a, J.b,
+                          J.s, J.What, J.bpart, 0, DM, nullptr, J.rn);
 }
 
 // d > 128: one wave per block, each lane's row in LDS (column-major, 64 KB);
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(kWave) void k_p2_valu_wide(
     const float* __restrict__ Y, const float* __restrict__ w, const float* __restrict__ aux,
     const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt, const int32_t* __restrict__ csize, int k,
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
-    float* __restrict__ What, double* __restrict__ bpart) {
+    float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ rn) {
   __shared__ float xs[kWideDM * kWave];
   __shared__ double sh[1];
   const int e = blockIdx.x * kWave + threadIdx.x;
@@ -160,18 +185,10 @@ __global__ __launch_bounds__(kWave) void k_p2_valu_wide(
   const int er = valid ? e : n - 1;
   float* xl = xs + threadIdx.x;
   const float* xr = X + (size_t)er * d;
-  float s2 = 0.f;
-  for (int c = 0; c < kWideDM; ++c) {
-    const float v = c < d ? xr[c] : 0.0f;
-    xl[c * kWave] = v;
-    s2 = fmaf(v, v, s2);
-  }
-  float ux = 0.f;
-  if (M == kCos) {  // unit vector (zero stays zero, with u = 0.5)
-    const float rx = s2 > 0.f ? 1.0f / sqrtf(s2) : 0.f;
-    ux = s2 > 0.f ? 0.f : 0.5f;
-    for (int c = 0; c < kWideDM; ++c) xl[c * kWave] *= rx;
-  }
+  // cosine: the row times its reciprocal norm (zero stays zero, u = 0.5)
+  const float rx = M == kCos ? rn[er] : 1.0f;
+  for (int c = 0; c < kWideDM; ++c) xl[c * kWave] = c < d ? xr[c] * rx : 0.0f;
+  const float ux = (M == kCos && !(rx > 0.f)) ? 0.5f : 0.f;
   const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
   double w_own = 0.0;
   double bmin = __builtin_inf();
@@ -232,7 +249,7 @@ static void launch_one(hipStream_t st, const P2Args& A, int c0 = 0, int ystride 
   const int blocks = (int)ceil_div(A.n, kP2Rows);
   hipLaunchKernelGGL((k_p2_valu<M, DM, PASS>), dim3(blocks), dim3(kP2Rows), 0, st, A.X, A.n, A.d, A.labels,
                      A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What, A.bpart, c0,
-                     ystride, A.Wpart);
+                     ystride, A.Wpart, A.rn);
 }
 
 template <int M>
@@ -253,8 +270,35 @@ static bool launch_metric(hipStream_t st, int DM, const P2Args& A) {
       }
       hipLaunchKernelGGL(k_p2_valu_wide<M>, dim3((int)ceil_div(A.n, kWave)), dim3(kWave), 0, st, A.X, A.n, A.d,
                          A.labels, A.Y, A.w, A.aux, A.sp_off, A.cnt, A.csize, A.k, A.a, A.b, A.s, A.What,
-                         A.bpart);
+                         A.bpart, A.rn);
       return true;
+    default: return false;
+  }
+}
+
+template <int M>
+static bool launch_jobs_metric(hipStream_t st, int DM, const P2Job* jobs, const int2* items, int nitems) {
+  switch (DM) {
+    case 8: hipLaunchKernelGGL((k_p2_valu_jobs<M, 8>), dim3(nitems), dim3(kP2Rows), 0, st, jobs, items); return true;
+    case 16: hipLaunchKernelGGL((k_p2_valu_jobs<M, 16>), dim3(nitems), dim3(kP2Rows), 0, st, jobs, items); return true;
+    case 32: hipLaunchKernelGGL((k_p2_valu_jobs<M, 32>), dim3(nitems), dim3(kP2Rows), 0, st, jobs, items); return true;
+    case 64: hipLaunchKernelGGL((k_p2_valu_jobs<M, 64>), dim3(nitems), dim3(kP2Rows), 0, st, jobs, items); return true;
+    case 128:
+      hipLaunchKernelGGL((k_p2_valu_jobs<M, 128>), dim3(nitems), dim3(kP2Rows), 0, st, jobs, items);
+      return true;
+    default: return false;
+  }
+}
+
+bool phase2_valu_jobs_ok(int metric, int DM) { return metric >= 0 && metric <= 3 && DM >= 8 && DM <= 128; }
+
+bool launch_phase2_valu_jobs(hipStream_t st, int metric, int DM, const P2Job* jobs, const int2* items, int nitems) {
+  if (nitems <= 0) return true;
+  switch (metric) {
+    case kEucl: return launch_jobs_metric<kEucl>(st, DM, jobs, items, nitems);
+    case kCos: return launch_jobs_metric<kCos>(st, DM, jobs, items, nitems);
+    case kManh: return launch_jobs_metric<kManh>(st, DM, jobs, items, nitems);
+    case kCanb: return launch_jobs_metric<kCanb>(st, DM, jobs, items, nitems);
     default: return false;
   }
 }

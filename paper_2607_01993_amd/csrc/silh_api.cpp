@@ -106,6 +106,7 @@ struct silh_ctx {
   int32_t* uh = nullptr;
   int32_t* perm = nullptr;
   int32_t* slab = nullptr;
+  float* rn = nullptr;  // cosine: reciprocal row norms of X
   double* q = nullptr;
 
   // sample
@@ -472,7 +473,14 @@ silh_status build_index(silh_ctx* c) {
     Carve cv;
     cv.add(&c->csize, (size_t)k).add(&c->bad, 1).add(&c->off, (size_t)k + 1).add(&c->q, (size_t)k);
     cv.add(&c->uh, (size_t)units * k).add(&c->perm, (size_t)n).add(&c->slab, (size_t)n);
+    if (c->prm.metric == SILH_COS) cv.add(&c->rn, (size_t)n);
     CHK(cv.commit(c, c->alloc_init));
+  }
+  if (c->rn) {
+    // cosine rows are made unit length by one float32 factor per row, the
+    // same for the element rows of Phase 2 and the packed sample rows
+    launch_rnorm(c->st, c->X, n, c->d, c->rn);
+    HIPCHK(hipGetLastError());
   }
   HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
   // cluster sizes from the sort's per-unit histograms (no separate count pass)
@@ -610,7 +618,7 @@ silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
   {
     Launch L(c, K_PACK);
     launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, c->d, c->DM, c->p_gid, c->s_off,
-                c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, (int)c->S_pad, c->gid_view, c->gid_pk,
+                c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, c->rn, (int)c->S_pad, c->gid_view, c->gid_pk,
                 c->w32, c->aux32, c->Y32);
     CHK(L.done());
   }
@@ -874,6 +882,7 @@ silh_status run_phase2(silh_ctx* c, float* a, float* b, float* s, float* What, d
   A.s = s;
   A.What = What;
   A.bpart = c->bpart;
+  A.rn = c->rn;
   free_list(c, c->alloc_p2);
   if (!c->mfma && phase2_valu_split(c->prm.metric, c->DM)) {
     Carve cv;
@@ -912,7 +921,7 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   const int64_t cap = m < n ? m : n;  // distinct rows
   int32_t *mark = nullptr, *pos = nullptr, *tmp = nullptr, *urows = nullptr, *ls = nullptr, *gsub = nullptr;
   int* bad = nullptr;
-  float *Xs = nullptr, *au = nullptr, *bu = nullptr, *su = nullptr;
+  float *Xs = nullptr, *au = nullptr, *bu = nullptr, *su = nullptr, *rnu = nullptr;
   double *bpu = nullptr, *bpm = nullptr, *mean_d = nullptr;
   const int64_t nbm = ceil_div(m, kRowsBlock);
   {
@@ -921,6 +930,7 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
     cv.add(&urows, (size_t)cap).add(&bad, 1).add(&Xs, (size_t)cap * d).add(&ls, (size_t)cap);
     cv.add(&gsub, (size_t)c->S_pad).add(&au, (size_t)cap).add(&bu, (size_t)cap).add(&su, (size_t)cap);
     cv.add(&bpu, (size_t)ceil_div(cap, c->p2_rows)).add(&bpm, (size_t)nbm).add(&mean_d, 1);
+    if (c->rn) cv.add(&rnu, (size_t)cap);
     CHK(cv.commit(c, c->alloc_rows));
   }
   HIPCHK(hipMemsetAsync(mark, 0, (size_t)n * sizeof(int32_t), c->st));
@@ -937,6 +947,7 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   launch_rows_compact(c->st, mark, pos, n, urows);
   launch_rows_gather(c->st, c->X, c->labels, d, urows, mu, Xs, ls);
   launch_rows_remap(c->st, c->gid_pk, c->S_pad, urows, mu, gsub);
+  if (rnu) launch_rnorm(c->st, Xs, mu, d, rnu);  // the same factors as for the rows of X
   HIPCHK(hipGetLastError());
   P2Args A;
   A.X = Xs;
@@ -956,6 +967,7 @@ silh_status rows_phase2(silh_ctx* c, const int32_t* rows, int64_t m, float* a, f
   A.s = su;
   A.What = nullptr;
   A.bpart = bpu;
+  A.rn = rnu;
   if (!c->mfma && phase2_valu_split(c->prm.metric, c->DM)) {
     Carve cv;
     cv.add(&A.Wpart, (size_t)(mu > 0 ? mu : 1) * c->k);

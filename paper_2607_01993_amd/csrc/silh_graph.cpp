@@ -66,6 +66,7 @@ struct silh_graph {
   int64_t bytes = 0;
   double* means_d = nullptr;
   int32_t* status_d = nullptr;
+  float* rn = nullptr;  // cosine: reciprocal row norms of X, computed once per replay
   double* means_h = nullptr;    // pinned
   int32_t* status_h = nullptr;  // pinned
   hipStream_t cap_st = nullptr;
@@ -198,7 +199,7 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
   launch_sample_sizes(st, b.s_off, k, (int)g->S_cap, b.cnt, b.sp_off, b.status);
   launch_clear_rows(st, b.sp_off + k, (int)g->S_cap, DM, b.gid_pk, b.w32, b.aux32, b.Y32);
   launch_pack(st, b.perm, b.slab, b.flag, b.pos, n, g->X, d, DM, b.p_gid, b.s_off, b.sp_off,
-              metric == SILH_COS ? 1 : 0, (int)g->S_cap, b.gid_view, b.gid_pk, b.w32, b.aux32, b.Y32);
+              metric == SILH_COS ? 1 : 0, g->rn, (int)g->S_cap, b.gid_view, b.gid_pk, b.w32, b.aux32, b.Y32);
   // Phase 2 and the mean (the block shape does not change the results)
   P2Args A;
   A.X = g->X;
@@ -217,6 +218,7 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
   A.What = nullptr;
   A.bpart = b.bpart;
   A.Wpart = b.Wpart;
+  A.rn = g->rn;
   if (g->mfma) {
     launch_center(st, b.Y32, DM, g->KP, b.sp_off, b.cnt, k, b.mu);
     if (!launch_pack_mfma(st, metric, g->mprec, DM, b.Y32, b.aux32, b.sp_off, b.cnt, k, b.mu, (int)g->S_cap, b.Ym,
@@ -301,6 +303,7 @@ silh_status silh_graph_create(const silh_params* base, const float* X, const int
                     : 0;
   g->br.resize((size_t)chains);
   bool ok = take(g, g->means_d, K) && take(g, g->status_d, K);
+  if (ok && base->metric == SILH_COS) ok = take(g, g->rn, g->n);
   for (Branch& b : g->br) ok = ok && alloc_branch(g, b);
   if (!ok) {
     release(g);
@@ -322,6 +325,7 @@ silh_status silh_graph_create(const silh_params* base, const float* X, const int
   bool built = hipStreamBeginCapture(g->cap_st, hipStreamCaptureModeThreadLocal) == hipSuccess;
   bool captured = built;
   if (built) {
+    if (g->rn) launch_rnorm(g->cap_st, g->X, g->n, g->d, g->rn);  // X is read at every replay
     built = hipEventRecord(g->fork, g->cap_st) == hipSuccess;
     for (Branch& b : g->br) built = built && hipStreamWaitEvent(b.st, g->fork, 0) == hipSuccess;
     for (int32_t i = 0; i < K && built; ++i) built = enqueue(g, g->br[(size_t)i % g->br.size()], i);

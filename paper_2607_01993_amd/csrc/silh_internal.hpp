@@ -71,13 +71,16 @@ void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t*
                  uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
                  double* p_gid, int32_t* flag, DistStore ds = {});
 void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, int32_t* flag);
+// rn[i] = 1 / |X_i| in float32 (fused chain in coordinate order, correctly
+// rounded square root and division), 0 for a zero row
+void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn);
 // Scatter the selected elements into the cluster-blocked, padded sample.
-// mode 0: raw coordinates; 1: rows scaled to unit L2 norm (cosine).  Rows at
+// mode 0: raw coordinates; 1: rows times rn (unit L2 norm, cosine).  Rows at
 // or past `cap` (the capacity of the packed arrays) are not written.
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
                  const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
-                 const int32_t* s_off, const int32_t* sp_off, int mode, int cap, int64_t* gid_view,
-                 int32_t* gid_pk, float* w32, float* aux32, float* Y32);
+                 const int32_t* s_off, const int32_t* sp_off, int mode, const float* rn, int cap,
+                 int64_t* gid_view, int32_t* gid_pk, float* w32, float* aux32, float* Y32);
 
 // ---- Phase 2 -----------------------------------------------------------------
 struct P2Args {
@@ -98,9 +101,41 @@ struct P2Args {
   float* What;          // [n][k] or null
   double* bpart;        // [ceil(n / rows per partial)]
   double* Wpart = nullptr;  // [n][k] float64, for the split vector-ALU pass (d > 128)
+  const float* rn = nullptr;  // [n] cosine: reciprocal row norms (launch_rnorm) of X's rows
+};
+// One request's Phase-2 launch as a work source of a multi-request launch
+// (the arguments of P2Args and of the matrix-core operands, in device memory).
+struct P2Job {
+  const float* X;
+  const int32_t* labels;
+  const void* Ym;        // matrix-core operands (null on the vector-ALU path)
+  const float* w;
+  const int32_t* gid_pk;
+  const int32_t* sp_off;
+  const int32_t* cnt;
+  const int32_t* csize;
+  const float* mu;
+  float* a;
+  float* b;
+  float* s;
+  float* What;
+  double* bpart;
+  const float* bnorm;
+  const float* Y32;
+  const float* aux;
+  const float* rn;
+  int n, d, k, pad0;
 };
 // returns false if (metric, d) has no VALU kernel
 bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& a);
+// Multi-request launches: workgroup i runs work item items[i] = (index into
+// jobs, block of that job's own launch).  The vector-ALU form covers the
+// one-pass shapes with the row in registers (phase2_valu_jobs_ok); blocks
+// are phase2_valu_rows / phase2_mfma_rows * pb elements.
+bool launch_phase2_valu_jobs(hipStream_t st, int metric, int DM, const P2Job* jobs, const int2* items, int nitems);
+bool phase2_valu_jobs_ok(int metric, int DM);
+bool launch_phase2_mfma_jobs(hipStream_t st, int metric, int prec, int DM, int pb, const P2Job* jobs,
+                             const int2* items, int nitems);
 int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if unsupported
 // elements per block (and per partial of the mean) of the VALU kernel
 int phase2_valu_rows(int metric, int DM);

@@ -80,11 +80,12 @@ struct Bufs {
   float *w32 = nullptr, *aux32 = nullptr, *Y32 = nullptr, *mu = nullptr, *bnorm = nullptr;
   unsigned char* Ym = nullptr;
   double *bpart = nullptr, *Wpart = nullptr, *mean = nullptr;
+  float* rn = nullptr;
 };
 
 struct Shape {
   int n, d, k, DM, KP, mprec, p2_rows, seg, units;
-  bool mfma, split;
+  bool mfma, split, cos;
   int64_t S_cap;
 };
 
@@ -100,6 +101,7 @@ void layout(const Shape& s, Slices& sl, Bufs& b) {
     sl.add(&b.mu, k * s.KP).add(&b.bnorm, s.S_cap).add(&b.Ym, s.S_cap * s.KP * elem);
   }
   if (s.split) sl.add(&b.Wpart, n * k);
+  if (s.cos) sl.add(&b.rn, n);
 }
 
 }  // namespace
@@ -122,6 +124,7 @@ extern "C" silh_status silh_exact_noalloc(const silh_params* prm, const float* X
   sh.KP = sh.mfma ? mfma_kp(sh.mprec, sh.DM) : 0;
   sh.p2_rows = sh.mfma ? phase2_mfma_rows(sh.mprec, sh.DM) : phase2_valu_rows(prm->metric, sh.DM);
   sh.split = !sh.mfma && phase2_valu_split(prm->metric, sh.DM);
+  sh.cos = prm->metric == SILH_COS;
   sh.seg = sort_seg(sh.n, sh.k);
   sh.units = (int)ceil_div(sh.n, sh.seg);
   sh.S_cap = (int64_t)sh.n + (int64_t)kSamplePad * sh.k;  // every element, each cluster padded
@@ -165,6 +168,7 @@ extern "C" silh_status silh_exact_noalloc(const silh_params* prm, const float* X
   launch_unit_scan(st, B.uh, sh.units, k, B.csize);
   launch_index_sizes(st, B.csize, k, 0.0, B.off, B.q, B.status);
   launch_scatter(st, labels, n, k, sh.seg, B.uh, B.off, B.perm, B.slab);
+  if (B.rn) launch_rnorm(st, X, n, d, B.rn);
   // every element sampled with p = 1 (Section 2: the exact sums)
   launch_fill_all(st, B.perm, n, B.p_gid, B.flag);
   launch_scan(st, B.flag, n, B.pos, B.scan_tmp);
@@ -172,7 +176,7 @@ extern "C" silh_status silh_exact_noalloc(const silh_params* prm, const float* X
   launch_sample_sizes(st, B.s_off, k, (int)sh.S_cap, B.cnt, B.sp_off, B.status);
   launch_clear_rows(st, B.sp_off + k, (int)sh.S_cap, DM, B.gid_pk, B.w32, B.aux32, B.Y32);
   launch_pack(st, B.perm, B.slab, B.flag, B.pos, n, X, d, DM, B.p_gid, B.s_off, B.sp_off, metric == SILH_COS ? 1 : 0,
-              (int)sh.S_cap, B.gid_view, B.gid_pk, B.w32, B.aux32, B.Y32);
+              B.rn, (int)sh.S_cap, B.gid_view, B.gid_pk, B.w32, B.aux32, B.Y32);
   P2Args A;
   A.X = X;
   A.n = n;
@@ -192,6 +196,7 @@ extern "C" silh_status silh_exact_noalloc(const silh_params* prm, const float* X
   A.What = nullptr;
   A.bpart = B.bpart;
   A.Wpart = B.Wpart;
+  A.rn = B.rn;
   bool ok = true;
   if (sh.mfma) {
     launch_center(st, B.Y32, DM, sh.KP, B.sp_off, B.cnt, k, B.mu);
