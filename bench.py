@@ -66,15 +66,23 @@ def phase2_roofline(metric, prec, d, n, S, kern_s):
     times the per-pair figure) over the average launch duration."""
     pairs = float(n) * S
     if metric == "eucl" and prec == "bf16":
-        # bound by the square root per pair (transcendental rate); the MFMA
-        # contraction (2d flops per pair) is reported beside it
-        ach = pairs / kern_s / 1e12
-        return {"bound": "alu", "achieved": ach, "peak": PEAK["sqrt_tops"], "unit": "TFLOP/s",
-                "frac": ach / PEAK["sqrt_tops"], "work": "1 square root per pair (counted as 1 flop)",
-                "mfma": {"achieved": 2 * d * pairs / kern_s / 1e12, "peak": PEAK["bf16_mfma_tflops"],
-                         "unit": "TFLOP/s", "frac": 2 * d * pairs / kern_s / 1e12 / PEAK["bf16_mfma_tflops"]}}
-    if metric in ("eucl", "cos") and prec in ("fp32", "bf16"):
-        pk = PEAK["fp32_mfma_tflops"] if prec == "fp32" else PEAK["bf16_mfma_tflops"]
+        # two ceilings: the square root per pair (transcendental rate) and
+        # the MFMA contraction (2d flops per pair); the nearer one governs
+        # (the square root at d = 32, the matrix cores at d = 256), the
+        # other is reported beside it
+        sq = pairs / kern_s / 1e12
+        mf = 2 * d * pairs / kern_s / 1e12
+        sqrt_roof = {"bound": "alu", "achieved": sq, "peak": PEAK["sqrt_tops"], "unit": "TFLOP/s",
+                     "frac": sq / PEAK["sqrt_tops"], "work": "1 square root per pair (counted as 1 flop)"}
+        mfma_roof = {"bound": "mfma", "achieved": mf, "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
+                     "frac": mf / PEAK["bf16_mfma_tflops"], "work": f"2d = {2 * d} MFMA flops per pair"}
+        if sqrt_roof["frac"] >= mfma_roof["frac"]:
+            sqrt_roof["mfma"] = {x: mfma_roof[x] for x in ("achieved", "peak", "unit", "frac")}
+            return sqrt_roof
+        mfma_roof["sqrt"] = {x: sqrt_roof[x] for x in ("achieved", "peak", "unit", "frac")}
+        return mfma_roof
+    if metric in ("eucl", "cos") and prec in ("fp32", "bf16", "fp8"):
+        pk = {"fp32": PEAK["fp32_mfma_tflops"], "bf16": PEAK["bf16_mfma_tflops"], "fp8": PEAK["fp8_mfma_tflops"]}[prec]
         ach = 2 * d * pairs / kern_s / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
                 "work": f"2d = {2 * d} MFMA flops per pair"}
@@ -86,31 +94,76 @@ def phase2_roofline(metric, prec, d, n, S, kern_s):
             "frac": ach / PEAK["fp32_vec_tflops"], "work": f"{per} flops per pair"}
 
 
-def cpu_baseline(X, L, k, metric, t, seed, n_rows=2048):
-    """The float64 oracle on a bounded sample of the same workload: Phase 1
-    on all rows, Phase 2 on n_rows seeded rows, extrapolated to all n rows."""
+def _oracle_rows(args):
+    import oracle
+    X, L, k, metric, smp, rows = _CPU_STATE["job"]
+    return oracle.estimate(X, L, k, metric, smp, rows=rows[args[0]:args[1]])["s"].shape[0]
+
+
+_CPU_STATE = {}
+
+
+def cpu_baseline(X, L, k, metric, t, seed, n_rows=16384, procs=None):
+    """The float64 oracle, as it stands, on a bounded sample of the same
+    workload: Phase 1 on all rows (one process), Phase 2 on n_rows seeded
+    rows, extrapolated to all n rows (rows are independent in Phase 2).
+    Phase 2 is timed twice: in one process, and split over `procs` forked
+    processes (the host's cores, at most 16).  Runs before the GPU is
+    touched, so forking is safe."""
+    import multiprocessing as mp
+
     import numpy as np
 
     import oracle
     n = X.shape[0]
+    procs = procs or min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     smp = oracle.sample(X, L, k, metric, t, 0.01, seed, "pps")
     t1 = time.perf_counter()
     rows = np.sort(np.random.default_rng(123).choice(n, n_rows, replace=False))
     oracle.estimate(X, L, k, metric, smp, rows=rows)
     t2 = time.perf_counter()
+    _CPU_STATE["job"] = (X, L, k, metric, smp, rows)
+    step = (n_rows + procs - 1) // procs
+    with mp.get_context("fork").Pool(procs) as pool:
+        t3 = time.perf_counter()
+        pool.map(_oracle_rows, [(a, min(n_rows, a + step)) for a in range(0, n_rows, step)])
+        t4 = time.perf_counter()
     S = sum(f.shape[0] for f in smp["F"])
     p1 = sum(int(m.shape[0]) * int(f.shape[0]) for m, f in zip(smp["members"], smp["F0"]))
-    t_full = (t1 - t0) + (t2 - t1) * n / n_rows
+    one = (t1 - t0) + (t2 - t1) * n / n_rows
+    many = (t1 - t0) + (t4 - t3) * n / n_rows
     return {
-        "value": (n * S + p1) / t_full,
+        "value": (n * S + p1) / many,
         "unit": "weighted dist evals/s",
-        "cores": 1,
+        "cores": procs,
         "kind": "oracle",
-        "sample": f"Phase 1 on all n={n} rows ({t1 - t0:.1f} s) + Phase 2 on {n_rows} seeded rows "
-                  f"({t2 - t1:.1f} s), Phase 2 time scaled by n/{n_rows}; NumPy float64, one thread "
-                  f"(host reports {os.cpu_count()} cores)",
+        "sample": f"Phase 1 on all n={n} rows (one process, {t1 - t0:.1f} s) + Phase 2 on {n_rows} seeded rows "
+                  f"over {procs} forked processes ({t4 - t3:.2f} s), Phase 2 time scaled by n/{n_rows}; NumPy "
+                  f"float64 (host reports {os.cpu_count()} cores)",
+        "one_thread": {"value": (n * S + p1) / one, "cores": 1,
+                       "sample": f"same, Phase 2 in one process ({t2 - t1:.1f} s)"},
     }
+
+
+def golden_mean(X, L, workload, metric):
+    """The float64 oracle's full-size Eq. 9 mean stored in
+    tests/golden/fullsize_means.json (written from oracle/ only), if it was
+    computed from these very arrays; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_means.json")
+    try:
+        with open(path) as f:
+            cases = json.load(f)["cases"]
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    h.update(X.tobytes())
+    h.update(L.tobytes())
+    for c in cases:
+        if c["workload"] == workload and c["metric"] == metric and c["data_sha256"] == h.hexdigest():
+            return c["mean"]
+    return None
 
 
 def run_steps(native, Xd, Ld, k, metric, prec, t, seed, steps, warmup, out_a, out_b, out_s):
@@ -202,6 +255,47 @@ def run_graph(native, Xd, Ld, k, metric, prec, t, seed, steps, warmup, work, eag
                     "the mean back"}
 
 
+def run_leg(native, Xd, Ld, k, metric, prec, t, seed, steps, a, b, s, work_fn=None, gold=None):
+    """A request workload other than the headline: steps requests (one
+    warm-up), step time, Phase-2 launch time, its roofline, |mean - oracle|."""
+    import numpy as np
+    r = run_steps(native, Xd, Ld, k, metric, prec, t, seed, steps, 1, a, b, s)
+    c2, m2 = r["stats"].get("phase2", (0, 0.0))
+    n, d = Xd.shape
+    sizes = np.bincount(Ld.cpu().numpy(), minlength=k)
+    p1 = int((sizes * np.diff(r["info"]["f0_offsets"])).sum())
+    work = n * r["S"] + p1
+    out = {"value": work / (r["t_all"] / steps), "ms_per_step": r["t_all"] / steps * 1e3,
+           "phase2_ms": m2 / max(c2, 1), "S": r["S"], "s_mean": r["mean"],
+           "phase2_roofline": phase2_roofline(metric, prec, d, n, r["S"], m2 / max(c2, 1) / 1e3)}
+    if gold is not None:
+        out["oracle_mean"] = gold
+        out["abs_delta_vs_oracle"] = abs(r["mean"] - gold)
+    return out
+
+
+def run_serving(native, torch, requests=48, load=0.5):
+    """A short serving run: the resident 32-dataset pool, `requests` requests
+    queued at once (saturation), then the same mix as Poisson arrivals at
+    load x saturation; p50/p99 latency overall and per metric."""
+    from paper_2607_01993_amd import serving
+    specs, data, reqs = serving.build_workload(requests, torch.device("cuda:0"))
+    srv = native.Server(workers=4, hbm_budget_bytes=96 << 30, batched=True)
+    ids = [srv.add_dataset(X) for X in data]
+    serving.run_closed(srv, ids, reqs)  # warm-up: block caches, and the autotuner's keys of every request
+    res, secs = serving.run_closed(srv, ids, reqs)
+    sat = len(reqs) / secs
+    pairs = float(sum(specs[r["dataset"]]["n"] * x["S"] for r, x in zip(reqs, res)))
+    rr = serving.run_poisson(srv, ids, reqs, load * sat, seed=11)
+    summary = serving.summarize(rr, reqs)
+    launches = srv.launches()
+    srv.close()
+    return {"requests": len(reqs), "saturation_req_s": sat, "weighted_dist_evals_per_s_closed": pairs / secs,
+            "rate_req_s": load * sat, "latency_ms": summary, "shared_launches": launches,
+            "note": "32 resident datasets (n 1e4..2e6, d 16/64/256, eucl/cos bf16, manh/canb fp32), Voronoi "
+                    "requests k 2..128, t 64/256/1024; Phase 2 of concurrent requests in shared launches"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +306,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=5,
                     help="steps of the float32 comparison run and of the Manhattan run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the directional (n = 4e6, d = 128), d = 256 and serving legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 256 MiB once first (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -227,6 +323,12 @@ def main():
 
     n, d, k, t, seed = (WORKLOAD[x] for x in ("n", "d", "k", "t", "seed"))
     X, L = synth.config_zipf_gauss(n=n, d=d, k=k, seed=seed)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the oracle's Phase 2 runs in forked processes
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(X, L, k, args.metric, t, seed)
+    gold = golden_mean(X, L, "zipf-gauss-blobs", args.metric)
     Xd = torch.from_numpy(X).cuda()
     Ld = torch.from_numpy(L).cuda()
     a = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -265,7 +367,8 @@ def main():
         compare[f"eucl_{ref_prec}"] = {
             "value": work / (r["t_all"] / args.compare_steps), "ms_per_step": r["t_all"] / args.compare_steps * 1e3,
             "phase2_ms": m2 / max(c2, 1), "s_mean": r["mean"],
-            "abs_delta_s_mean": abs(r["mean"] - main_run["mean"])}
+            "abs_delta_s_mean": abs(r["mean"] - main_run["mean"]),
+            "abs_delta_vs_oracle": abs(r["mean"] - gold) if gold is not None else None}
         r = run_steps(native, Xd, Ld, k, "manh", "fp32", t, seed, args.compare_steps, 1, a, b, s)
         c2, m2 = r["stats"].get("phase2", (0, 0.0))
         sz = np.diff(r["info"]["f0_offsets"])
@@ -274,6 +377,32 @@ def main():
             "value": w2 / (r["t_all"] / args.compare_steps), "ms_per_step": r["t_all"] / args.compare_steps * 1e3,
             "phase2_ms": m2 / max(c2, 1),
             "phase2_roofline": phase2_roofline("manh", "fp32", d, n, r["S"], m2 / max(c2, 1) / 1e3)}
+
+    if args.compare_steps > 0 and not args.no_large:
+        # the directional workload: n = 4e6, d = 128, k = 64 vMF blobs, t = 512, cosine
+        print("# generating the directional workload (n = 4e6, d = 128)", file=sys.stderr, flush=True)
+        Xv, Lv = synth.config_vmf_cos()
+        gv = golden_mean(Xv, Lv, "vmf-blobs", "cos")
+        Xvd, Lvd = torch.from_numpy(Xv).cuda(), torch.from_numpy(Lv).cuda()
+        del Xv, Lv
+        av = torch.empty(Xvd.shape[0], dtype=torch.float32, device="cuda")
+        bv, sv = torch.empty_like(av), torch.empty_like(av)
+        for prec, steps in (("bf16", args.compare_steps), ("fp8", args.compare_steps), ("fp32", 2)):
+            compare[f"vmf_n4e6_d128_k64_t512_cos_{prec}"] = run_leg(native, Xvd, Lvd, 64, "cos", prec, 512, 2,
+                                                                    steps, av, bv, sv, gold=gv)
+        del Xvd, Lvd, av, bv, sv
+        torch.cuda.empty_cache()
+        # long rows: n = 5e5, d = 256, k = 16 Zipf Gaussian blobs, t = 256, Euclidean bf16
+        Xw, Lw = synth.config_zipf_gauss(n=500_000, d=256, k=16, seed=4)
+        Xwd, Lwd = torch.from_numpy(Xw).cuda(), torch.from_numpy(Lw).cuda()
+        aw = torch.empty(Xwd.shape[0], dtype=torch.float32, device="cuda")
+        bw, sw = torch.empty_like(aw), torch.empty_like(aw)
+        compare["zipf_n5e5_d256_k16_t256_eucl_bf16"] = run_leg(native, Xwd, Lwd, 16, "eucl", "bf16", 256, 4,
+                                                               args.compare_steps, aw, bw, sw)
+        del Xwd, Lwd, aw, bw, sw
+        torch.cuda.empty_cache()
+        print("# serving leg", file=sys.stderr, flush=True)
+        compare["serving"] = run_serving(native, torch)
 
     if args.compare_steps > 0:
         compare["graph_replay"] = run_graph(native, Xd, Ld, k, args.metric, args.prec, t, seed, args.steps,
@@ -309,13 +438,11 @@ def main():
                               "from the timed steps",
         "roofline": roof,
         "s_mean": main_run["mean"],
+        "oracle_mean": gold,
+        "abs_delta_vs_oracle": abs(main_run["mean"] - gold) if gold is not None else None,
         "compare": compare,
+        "cpu_baseline": cpu,
     }
-    if not args.no_cpu_baseline:
-        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(X, L, k, args.metric, t, seed)
-    else:
-        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -263,20 +263,25 @@ silh_status silh_exact_rows(const silh_params* prm, const float* X, const int32_
 silh_status silh_coh_sep(silh_ctx* ctx, const float* W_hat, double* coh_host, double* sep_host);
 
 /*
- * Autotuning of the matrix-core Phase-2 kernel's block shape (one or two
- * 32-element blocks per wave), process-wide:
- *  mode 0  the built-in choice (two for float32 operands with d <= 32);
+ * Autotuning of the matrix-core Phase-2 kernel's block shape, process-wide.
+ * Shapes: 1 one 32-element block per wave; 2 two blocks per wave (d <= 64,
+ * not fp8); 3 one block per wave with the other number of tiles per stage
+ * (one or two 32-row sample tiles between block barriers) on the shapes that
+ * stage sample tiles in LDS (bf16 / float32 with d >= 64, fp8 with d >= 128).
+ *  mode 0  the built-in choice (two blocks for float32 operands with
+ *          d <= 32 and for cosine bf16 at d = 32, else one);
  *  mode 1  (default) on the first launch for a key (metric, operand type, d
  *          rounded up as in the kernels, floor(log2) of the padded sample
- *          size) time both shapes once, keep the faster; setting mode 1
- *          again forgets the measurements;
- *  mode 2 / 3  always one / two.
+ *          size) time every valid shape twice, keep the fastest; setting
+ *          mode 1 again forgets the measurements;
+ *  mode 2 / 3 / 4  always shape 1 / 2 / 3 where valid (else the built-in).
  * Results do not depend on the shape (the partial sums of the mean are per
- * 128 elements, added in the same order, in every shape).  SILH_E_ARG for a mode outside [0, 3].
+ * 128 elements, added in the same order, in every shape).  SILH_E_ARG for a
+ * mode outside [0, 4].
  */
 silh_status silh_set_tuning(int mode);
 
-/* *pb = the measured shape for that key (1 or 2), 0 if none yet. */
+/* *pb = the measured shape id for that key (1, 2 or 3), 0 if none yet. */
 silh_status silh_tuning_choice(int metric, int prec, int d, int64_t S_pad, int* pb);
 
 /* Read-only view of a context's Phase-1 result (for inspection and tests). */

@@ -84,6 +84,18 @@ typedef struct {
 } silh_graph_info;
 silh_status silh_graph_get_info(const silh_graph* g, silh_graph_info* out);
 
+/*
+ * silh_graph_choice - the Phase-2 block shape captured for clustering i (the
+ * ids of silh_tuning_choice: 1 one 32-element block per wave, 2 two, 3 one
+ * with the other number of tiles per LDS stage) and the padded sample size
+ * of the request it was tuned on.  Before capture, silh_graph_create runs one
+ * eager request per group of clusterings with equal floor(log2(k t)) and
+ * takes the autotuner's shape for it (silh_set_tuning's mode applies; with
+ * the float32 vector-ALU kernels the shape is 1 and the size 0).
+ * SILH_E_ARG for NULL arguments or i outside [0, K).
+ */
+silh_status silh_graph_choice(const silh_graph* g, int32_t i, int32_t* shape, int64_t* probe_S_pad);
+
 /* Free the graph and every buffer (through the allocator hooks).  NULL is a
  * no-op. */
 void silh_graph_destroy(silh_graph* g);

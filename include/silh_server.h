@@ -8,10 +8,22 @@
  * silh_pps_sample, silh_scores of silh.h, with the same kernels and results).
  * A request may instead ask for the subsampled estimate of Eq. 10 (silh.h's
  * silh_draw_rows and silh_scores_rows).
- * Requests are admitted first in, first out while the device memory they are
- * estimated to need fits the configured budget, and run concurrently on
- * worker threads, each with its own HIP stream and its own cache of device
- * blocks (returned to the device only by silh_server_destroy).
+ * Requests are admitted in arrival order while the device memory they are
+ * estimated to need fits the configured budget (a request that does not fit
+ * lets later ones that do go first, up to 8 times, then holds the queue until
+ * it fits).  Worker threads, each with its own HIP stream and its own cache
+ * of device blocks (trimmed after every request to budget / (2 workers)
+ * bytes of free blocks), run the cluster index and Phase 1 of admitted
+ * requests.  In mode 0 a batcher thread then runs the Phase 2 of every
+ * request whose Phase 1 is done in shared launches: each launch takes about
+ * 4 ms of (request, block-of-rows) work items of one kernel class (metric,
+ * operands, width), the request with the least remaining work first and at
+ * least a quarter for the oldest one, so a request arriving while others are
+ * on the device joins the next launch and a small request does not wait for
+ * a large one to end.  Each work item computes exactly what that block of
+ * the request's own launch computes, so results equal a direct call's.
+ * Requests with the row draws of Eq. 10, and vector-ALU shapes with d > 128,
+ * run their own Phase-2 launch on their worker.
  *
  * All calls are thread-safe.  Timestamps are nanoseconds of one steady clock
  * (silh_server_now_ns), so callers can schedule arrivals on the same clock.
@@ -30,9 +42,12 @@ extern "C" {
 typedef struct silh_server silh_server;
 
 typedef struct {
-  int32_t workers;           /* concurrent requests (worker threads / streams), 1..64 */
-  int32_t reserved0;         /* must be 0 */
-  uint64_t hbm_budget_bytes; /* device memory the in-flight requests may use (estimate) */
+  int32_t workers;           /* worker threads (each with its own stream) running the
+                                cluster index and Phase 1 of admitted requests, 1..64 */
+  int32_t mode;              /* 0: the Phase 2 of every request whose Phase 1 is done runs
+                                in shared launches over (request, row-block) work items;
+                                1: each request launches its own Phase 2 on its worker */
+  uint64_t hbm_budget_bytes; /* device memory the admitted requests may use (estimate) */
 } silh_server_cfg;
 
 typedef struct {
@@ -67,7 +82,7 @@ typedef struct {
 int64_t silh_server_now_ns(void);
 
 /* Create a server on the calling thread's current device.  SILH_E_ARG for
- * NULL arguments, workers outside [1, 64], reserved0 != 0 or a zero budget. */
+ * NULL arguments, workers outside [1, 64], mode outside [0, 1] or a zero budget. */
 silh_status silh_server_create(const silh_server_cfg* cfg, silh_server** out);
 
 /* Register a resident dataset: X [n][d] float32 row-major, device,
@@ -93,6 +108,10 @@ silh_status silh_server_drain(silh_server* srv);
 /* Drain, stop the workers, free their cached device blocks and streams.
  * NULL is a no-op. */
 void silh_server_destroy(silh_server* srv);
+
+/* Number of shared Phase-2 launches the batcher has issued so far (-1 for a
+ * NULL server). */
+int64_t silh_server_launches(silh_server* srv);
 
 /*
  * silh_sweep - s_hat_2 (Algorithm 1 and Eq. 9; with m > 0 the subsampled

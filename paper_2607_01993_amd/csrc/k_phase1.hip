@@ -571,7 +571,9 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
   const int dst = sp_off[j] + (ps - s_off[j]);
   if (dst >= cap || ps >= cap) return;  // capacity of the packed rows
   gid_view[ps] = g;
-  gid_pk[dst] = g;
+  // the packed row's element id, for the Phase-2 self-pair test (a zero row
+  // under cosine gets -1: its distance to itself is 1 by the cosine reading)
+  gid_pk[dst] = (mode == 1 && !(rn[g] > 0.0f)) ? -1 : g;
   w32[dst] = (float)(1.0 / p_gid[g]);
   const float* xr = X + (size_t)g * d;
   float* yr = Y32 + (size_t)dst * DM;

@@ -66,9 +66,7 @@ constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
 // cancellation.  tau = 2^-5 for float32 operands (relative error of d below
 // 2^-17 for the others) and 2^-8 for bf16 (whose own rounding of x~ and y~
 // dominates below that).  The self pair d(e, e) is one of them and comes out
-// exactly 0.  Cosine (unit rows, c scaled by 1/2) takes the same test; its
-// rows are the element's row times its reciprocal norm, the same product as
-// the packed sample row, so the self pair is exactly 0 there too.
+// exactly 0.
 template <int P>
 constexpr float kRecomputeThr = P == 0 ? 6.0f / 32.0f : 6.0f / 256.0f;
 
@@ -212,7 +210,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       row[c] = -2.0f * alpha * v;
     }
     const float bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
-    thr = kRecomputeThr<P> * alpha * ny;
+    thr = M == kEucl ? kRecomputeThr<P> * ny : 0.0f;
     if (P == 0) {
       row[DM] = 1.0f;
       row[DM + 1] = bn;
@@ -350,7 +348,8 @@ __device__ __forceinline__ void load_chunk(const float* __restrict__ xp, int c, 
 }
 
 // one tile's B operand (this lane's half row), weight and the sample's
-// value in bnorm (fp8: its norm term; Euclidean: its recompute threshold)
+// per-row value: fp8 its norm term, Euclidean its recompute threshold (both
+// in bnorm), cosine its element id (gid_pk)
 template <int M, int P, int DM>
 __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const float* __restrict__ w,
                                           const int32_t* __restrict__ gid_pk,
@@ -363,7 +362,7 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
   const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)row0 * (size_t)(C::KP * C::ELEM),
                           32 * C::KP * C::ELEM);
   const auto rw = rsrc_at(w + row0, 32 * 4);
-  const auto rg = rsrc_at(bnorm + row0, 32 * 4);
+  const auto rg = rsrc_at((M == kCos && P != 2) ? (const void*)(gid_pk + row0) : (const void*)(bnorm + row0), 32 * 4);
   if constexpr (P == 2) {
 #pragma unroll
     for (int s = 0; s < C::NSTEP; ++s) {
@@ -387,12 +386,18 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
 // waves per SIMD the one-block shapes from d = 32 on keep (their occupancy
 // without the recompute path, which must not lower it)
 template <int M, int P, int DM, int PB>
-constexpr int kMinWaves = (P == 2 || PB == 2 || DM < 32) ? 1 : DM == 32 ? (P == 1 ? 4 : 1) : DM == 64 ? 3 : DM == 128 ? 2 : 1;
+constexpr int kMinWaves = (M != kEucl || P == 2 || PB == 2 || DM < 32) ? 1
+                          : DM == 32 ? (P == 1 ? 4 : 1) : DM == 64 ? 3 : DM == 128 ? 2 : 1;
 
 // One block of the Phase-2 launch: 4 waves x PB x 32 elements, from element
 // blk * 128 * PB on.  The kernels below run it for blockIdx.x (one request)
 // or for the (request, block) work items of a multi-request launch.
-template <int M, int P, int DM, int PB>
+// tiles per LDS stage of the one-block shape by default: two where measured
+// faster (bf16 at d = 64, fp8), else one; the autotuner may try the other
+template <int P, int DM>
+constexpr int kTBDefault = (P == 2 || (P == 1 && DM == 64)) ? 2 : 1;
+
+template <int M, int P, int DM, int PB, int TBX>
 __device__ __forceinline__ void p2_mfma_block(
     const int blk, const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
@@ -419,7 +424,7 @@ __device__ __forceinline__ void p2_mfma_block(
   constexpr bool kLds = P == 2 ? C::HALF > 40 : C::HALF > 30;
   // tiles per LDS stage (one barrier per stage): two where it costs no wave
   // per SIMD and measured faster (bf16 at d = 64, fp8), else one
-  constexpr int kTB = (kLds && PB == 1 && (P == 2 || (P == 1 && DM == 64))) ? 2 : 1;
+  constexpr int kTB = (kLds && PB == 1) ? TBX : 1;
   __shared__ __attribute__((aligned(16))) unsigned char ldsB[kLds ? 2 * kTB * kTileB : 16];
   __shared__ float ldsW[2][kTB * 32];
   __shared__ int ldsG[2][kTB * 32];
@@ -609,7 +614,7 @@ __device__ __forceinline__ void p2_mfma_block(
           for (int s = 0; s < C::NSTEP; ++s)
             c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], getB(s), c, 0, 0, 0, 0, 0, 0);
         }
-        if constexpr (P != 2) {
+        if constexpr (P != 2 && M == kEucl) {
           // pairs prone to cancellation (kRecomputeThr) get their squared
           // distance again from the float32 rows; rare outside the self pair
           const float thr = __int_as_float(gj);
@@ -629,23 +634,27 @@ __device__ __forceinline__ void p2_mfma_block(
               const int e = e0 < n ? e0 : n - 1;
               const float* xp = X + (size_t)e * d;
               float acc2 = 0.0f;
-              if constexpr (M == kEucl) {
-                for (int q = 0; q < d; ++q) {
-                  const float t = xp[q] - yr[q];
-                  acc2 = fmaf(t, t, acc2);
-                }
-              } else {
-                // cosine: half the squared distance of the unit rows, plus u
-                const float rx = rn[e];
-                for (int q = 0; q < d; ++q) {
-                  const float t = xp[q] * rx - yr[q];
-                  acc2 = fmaf(t, t, acc2);
-                }
-                acc2 = fmaf(0.5f, acc2, (rx > 0.f ? 0.f : 0.5f) + aux[srow + col]);
+              for (int q = 0; q < d; ++q) {
+                const float t = xp[q] - yr[q];
+                acc2 = fmaf(t, t, acc2);
               }
 #pragma unroll
               for (int q = 0; q < 16; ++q) c[q] = q == r ? acc2 : c[q];
             }
+          }
+        } else if constexpr (P != 2) {
+          // cosine: no square root amplifies the expansion's absolute error
+          // (of order 2^-22 here), so only the self pair d(e, e) = 0 is
+          // forced: a column holding one of this block's own 32 elements (in
+          // this lane's half of the rows) zeroes that row.  The unit rows of
+          // both sides are the same product x * rn, so the pair's operands
+          // are identical; zero rows carry id -1 and keep their d = 1.
+          const int self = gj - (P0 + 32 * b);
+          if ((unsigned)self < 32u && ((self >> 2) & 1) == h) {
+            const int rh = ((self >> 3) << 2) | (self & 3);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              if (r == rh) c[r] = 0.0f;
           }
         }
         const float wt = P == 2 ? wj * (1.0f / S2) : wj;
@@ -687,7 +696,7 @@ __device__ __forceinline__ void p2_mfma_block(
           }
           if (threadIdx.x < 32) {
             sw[tt] = w[r0 + threadIdx.x];
-            sg[tt] = __float_as_int(bnorm[r0 + threadIdx.x]);
+            sg[tt] = (M == kCos && P != 2) ? gid_pk[r0 + threadIdx.x] : __float_as_int(bnorm[r0 + threadIdx.x]);
           }
         }
       };
@@ -803,7 +812,7 @@ __device__ __forceinline__ void p2_mfma_block(
   }
 }
 
-template <int M, int P, int DM, int PB>
+template <int M, int P, int DM, int PB, int TBX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma(
     const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
@@ -812,7 +821,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
     float* __restrict__ a_out, float* __restrict__ b_out, float* __restrict__ s_out,
     float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm,
     const float* __restrict__ Y32, int DMY, const float* __restrict__ aux, const float* __restrict__ rn) {
-  p2_mfma_block<M, P, DM, PB>(blockIdx.x, X, n, d, labels, Ym, w, gid_pk, sp_off, cnt, csize, k, mu, a_out, b_out,
+  p2_mfma_block<M, P, DM, PB, TBX>(blockIdx.x, X, n, d, labels, Ym, w, gid_pk, sp_off, cnt, csize, k, mu, a_out, b_out,
                               s_out, What, bpart, bnorm, Y32, DMY, aux, rn);
 }
 
@@ -825,7 +834,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
 // registers in the shapes from d = 32 on.  The job table and the items are
 // read through the constant address space, so their values sit in scalar
 // registers like kernel arguments.
-template <int M, int P, int DM, int PB>
+template <int M, int P, int DM, int PB, int TBX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma_jobs(
     const P2Job* __restrict__ jobs, const int2* __restrict__ items) {
   typedef const __attribute__((address_space(4))) P2Job* cjob_ptr;
@@ -833,48 +842,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
   const int jx = ((citem_ptr)items)[2 * blockIdx.x];
   const int blk = ((citem_ptr)items)[2 * blockIdx.x + 1];
   const auto& J = ((cjob_ptr)jobs)[jx];
-  p2_mfma_block<M, P, DM, PB>(blk, J.X, J.n, J.d, J.labels, J.Ym, J.w, J.gid_pk, J.sp_off, J.cnt, J.csize, J.k, J.mu,
+  p2_mfma_block<M, P, DM, PB, TBX>(blk, J.X, J.n, J.d, J.labels, J.Ym, J.w, J.gid_pk, J.sp_off, J.cnt, J.csize, J.k, J.mu,
                               J.a, J.b, J.s, J.What, J.bpart, J.bnorm, J.Y32, DM, J.aux, J.rn);
 }
 
-// 32-element blocks per wave (PB): two halve the B-operand loads per pair
-// (the float32 path is bound by the MFMA rate and gains) but double the
-// accumulator and A-operand registers (fewer waves per SIMD).  The default
-// below is the measured choice on the benchmark workload; the autotuner may
-// pick per (metric, operands, d, sample size).  fp8 always uses one.
+// Block shapes of the matrix-core kernel (ids used by the autotuner):
+//  1  one 32-element block per wave (on the LDS path with kTBDefault tiles
+//     per stage);
+//  2  two blocks per wave: half the B-operand loads per pair (the float32
+//     path is bound by the MFMA rate and gains) but twice the accumulator
+//     and A-operand registers (fewer waves per SIMD); d <= 64, not fp8;
+//  3  one block per wave with the other number of tiles per LDS stage (the
+//     LDS path only).
+// The arithmetic of every element, and the 128-element partials of the
+// mean, are the same in every shape.
+bool mfma_lds_path(int prec, int DM) {
+  return prec == 2 ? round_up_c(DM, 64) / 2 > 40 : mfma_kp(prec, DM) / 2 > 30;
+}
 int mfma_pb_default(int prec, int DM) { return (prec == 0 && DM <= 32) ? 2 : 1; }
 int mfma_pb_max(int prec, int DM) { return (prec == 2 || DM > 64) ? 1 : 2; }
+int mfma_shapes(int prec, int DM, int* ids) {
+  int m = 0;
+  ids[m++] = 1;
+  if (mfma_pb_max(prec, DM) == 2) ids[m++] = 2;
+  if (mfma_lds_path(prec, DM)) ids[m++] = 3;
+  return m;
+}
 
-template <int M, int P, int DM, int PB>
+template <int M, int P, int DM, int PB, int TBX>
 static void launch_mfma_pb(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
                            const float* bnorm) {
   const int blocks = (int)ceil_div(A.n, 128 * PB);
-  hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
+  hipLaunchKernelGGL((k_p2_mfma<M, P, DM, PB, TBX>), dim3(blocks), dim3(256), 0, st, A.X, A.n, A.d, A.labels, Ym,
                      A.w, A.gid_pk, A.sp_off, A.cnt, A.csize, A.k, mu, A.a, A.b, A.s, A.What, A.bpart,
                      bnorm, A.Y, DM, A.aux, A.rn);
 }
 
 template <int M, int P, int DM>
 static void launch_mfma_one(hipStream_t st, const P2Args& A, const float* mu, const void* Ym,
-                            const float* bnorm, int pb) {
+                            const float* bnorm, int shape) {
+  constexpr int TB0 = kTBDefault<P, DM>;
   if constexpr (P != 2 && DM <= 64) {  // two blocks per wave would not fit the registers beyond
-    if (pb == 2) {
-      launch_mfma_pb<M, P, DM, 2>(st, A, mu, Ym, bnorm);
+    if (shape == 2) {
+      launch_mfma_pb<M, P, DM, 2, 1>(st, A, mu, Ym, bnorm);
       return;
     }
   }
-  launch_mfma_pb<M, P, DM, 1>(st, A, mu, Ym, bnorm);
+  if (shape == 3 && mfma_lds_path(P, DM)) {
+    launch_mfma_pb<M, P, DM, 1, 3 - TB0>(st, A, mu, Ym, bnorm);
+    return;
+  }
+  launch_mfma_pb<M, P, DM, 1, TB0>(st, A, mu, Ym, bnorm);
 }
 
 template <int M, int P, int DM>
-static void launch_jobs_one(hipStream_t st, const P2Job* jobs, const int2* items, int nitems, int pb) {
+static void launch_jobs_one(hipStream_t st, const P2Job* jobs, const int2* items, int nitems, int shape) {
+  constexpr int TB0 = kTBDefault<P, DM>;
   if constexpr (P != 2 && DM <= 64) {
-    if (pb == 2) {
-      hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 2>), dim3(nitems), dim3(256), 0, st, jobs, items);
+    if (shape == 2) {
+      hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 2, 1>), dim3(nitems), dim3(256), 0, st, jobs, items);
       return;
     }
   }
-  hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 1>), dim3(nitems), dim3(256), 0, st, jobs, items);
+  if (shape == 3 && mfma_lds_path(P, DM)) {
+    hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 1, 3 - TB0>), dim3(nitems), dim3(256), 0, st, jobs, items);
+    return;
+  }
+  hipLaunchKernelGGL((k_p2_mfma_jobs<M, P, DM, 1, TB0>), dim3(nitems), dim3(256), 0, st, jobs, items);
 }
 
 template <int M, int P, int DM>
@@ -941,14 +975,14 @@ bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float*
 }
 
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
-                        const void* Ym, const float* bnorm, int pb) {
-  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym, bnorm, pb);
+                        const void* Ym, const float* bnorm, int shape) {
+  SILH_MFMA_DISPATCH(launch_mfma_one, st, A, mu, Ym, bnorm, shape);
 }
 
-bool launch_phase2_mfma_jobs(hipStream_t st, int metric, int prec, int DM, int pb, const P2Job* jobs,
+bool launch_phase2_mfma_jobs(hipStream_t st, int metric, int prec, int DM, int shape, const P2Job* jobs,
                              const int2* items, int nitems) {
   if (nitems <= 0) return true;
-  SILH_MFMA_DISPATCH(launch_jobs_one, st, jobs, items, nitems, pb);
+  SILH_MFMA_DISPATCH(launch_jobs_one, st, jobs, items, nitems, shape);
 }
 
 int phase2_mfma_rows(int, int) { return 128; }

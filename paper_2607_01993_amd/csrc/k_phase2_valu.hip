@@ -11,6 +11,8 @@
 // uniform too, so the per-cluster running sums need no cross-lane traffic.
 #include <float.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "silh_internal.hpp"
 
@@ -23,11 +25,14 @@ constexpr int kGroup = 32;  // samples summed in float32 before the float64 add
 // else 0): for unit x_hat, y_hat, 1 - x_hat.y_hat = |x_hat - y_hat|^2 / 2, and
 // the u terms give 1 whenever either vector is zero; this form does not
 // cancel for near-parallel pairs.
-template <int M>
+// Canberra's guard (G) keeps a 0/0 coordinate at 0 (den >= FLT_MIN); without
+// it the step is one instruction shorter, valid when |x_c| >= FLT_MIN for
+// every coordinate of the element row (then den > 0 whatever y is).
+template <int M, bool G = true>
 __device__ __forceinline__ float dist32_step(float s, float xc, float yc) {
   if (M == kManh) return s + fabsf(xc - yc);
   if (M == kCanb) {
-    const float den = fmaxf(fabsf(xc) + fabsf(yc), FLT_MIN);
+    const float den = G ? fmaxf(fabsf(xc) + fabsf(yc), FLT_MIN) : fabsf(xc) + fabsf(yc);
     return fmaf(fabsf(xc - yc), __builtin_amdgcn_rcpf(den), s);
   }
   const float df = xc - yc;  // Euclidean, cosine
@@ -42,12 +47,12 @@ __device__ __forceinline__ float dist32_final(float s, float ux, float uy) {
 }
 
 // the element's row in registers
-template <int M, int DM>
+template <int M, int DM, bool G = true>
 __device__ __forceinline__ float dist32(const float (&x)[DM], const float* __restrict__ y, float ux,
                                       float uy) {
   float s = 0.f;
 #pragma unroll
-  for (int c = 0; c < DM; ++c) s = dist32_step<M>(s, x[c], y[c]);
+  for (int c = 0; c < DM; ++c) s = dist32_step<M, G>(s, x[c], y[c]);
   return dist32_final<M>(s, ux, uy);
 }
 
@@ -95,22 +100,39 @@ __device__ __forceinline__ void p2_valu_block(
   }
   const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
 
+  // Canberra: the guard-free step when no element row of the wave has a
+  // coordinate below FLT_MIN in magnitude (padding coordinates are 0, so a
+  // padded row keeps the guard)
+  bool guard = true;
+  if (M == kCanb) {
+    bool nz = true;
+#pragma unroll
+    for (int c = 0; c < DM; ++c) nz = nz && fabsf(x[c]) >= FLT_MIN;
+    guard = !__all(nz);
+  }
   double w_own = 0.0;
   double bmin = __builtin_inf();
   for (int j = 0; j < k; ++j) {
     const int s0 = sp_off[j];
     const int cj = cnt[j];
     double accd = 0.0;
-    for (int g0 = 0; g0 < cj; g0 += kGroup) {
-      const int g1 = g0 + kGroup < cj ? g0 + kGroup : cj;
-      float acc = 0.f;
-      for (int q = g0; q < g1; ++q) {
-        const float* y = Y + (size_t)(s0 + q) * ystride + c0;
-        const float uy = M == kCos ? aux[s0 + q] : 0.f;
-        acc = fmaf(w[s0 + q], dist32<M, DM>(x, y, ux, uy), acc);
+    auto sweep = [&](auto g) {
+      constexpr bool G = decltype(g)::value;
+      for (int g0 = 0; g0 < cj; g0 += kGroup) {
+        const int g1 = g0 + kGroup < cj ? g0 + kGroup : cj;
+        float acc = 0.f;
+        for (int q = g0; q < g1; ++q) {
+          const float* y = Y + (size_t)(s0 + q) * ystride + c0;
+          const float uy = M == kCos ? aux[s0 + q] : 0.f;
+          acc = fmaf(w[s0 + q], dist32<M, DM, G>(x, y, ux, uy), acc);
+        }
+        accd += (double)acc;
       }
-      accd += (double)acc;
-    }
+    };
+    if (M == kCanb && !guard)
+      sweep(std::integral_constant<bool, false>{});
+    else
+      sweep(std::integral_constant<bool, true>{});
     if (PASS == 1) {
       if (valid) Wpart[(size_t)e * k + j] = accd;
       continue;

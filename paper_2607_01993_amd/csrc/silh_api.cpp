@@ -804,10 +804,11 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
 
 // ---- autotuning of the MFMA Phase-2 block shape ------------------------------
 // Key: (metric, operand type, padded row width, floor(log2(padded sample
-// size))).  On the first Phase-2 launch of a key both shapes run once on the
-// context's stream, timed with events, and the faster is kept for the
-// process.  Every shape writes the same values (each element's arithmetic
-// and the 128-element partials of the mean do not depend on it).
+// size))).  On the first Phase-2 launch of a key every valid shape (blocks
+// per wave, tiles per LDS stage: mfma_shapes) runs twice on the context's
+// stream, timed with events, and the fastest is kept for the process.  Every
+// shape writes the same values (each element's arithmetic and the
+// 128-element partials of the mean do not depend on it).
 std::mutex g_tune_mu;
 std::map<std::array<int, 4>, int> g_tune;
 std::atomic<int> g_tune_mode{1};
@@ -819,32 +820,39 @@ int size_bucket(int64_t S_pad) {
 }
 
 int pick_pb(silh_ctx* c, const P2Args& A) {
-  if (mfma_pb_max(c->mprec, c->DM) == 1) return 1;
+  int ids[3];
+  const int m = mfma_shapes(c->mprec, c->DM, ids);
   const int mode = g_tune_mode.load();
-  if (mode == 0) return pb_builtin(c->prm.metric, c->mprec, c->DM);
-  if (mode == 2 || mode == 3) return mode - 1;
+  if (mode == 0 || m == 1) return m == 1 ? 1 : pb_builtin(c->prm.metric, c->mprec, c->DM);
+  if (mode >= 2) {  // a fixed shape where valid, else the built-in one
+    for (int i = 0; i < m; ++i)
+      if (ids[i] == mode - 1) return ids[i];
+    return pb_builtin(c->prm.metric, c->mprec, c->DM);
+  }
   const std::array<int, 4> key{c->prm.metric, c->mprec, c->DM, size_bucket(c->S_pad)};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return it->second;
   }
-  // each shape launched twice, alternating, and the faster launch of each
-  // compared (one launch of each mis-picks when they are ~10 % apart)
-  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // each shape launched twice, in two rounds over the shapes, and the faster
+  // launch of each compared (one launch of each mis-picks when they are
+  // ~10 % apart)
+  hipEvent_t e[7] = {};
   bool ok = true;
-  for (auto& ev : e) ok = ok && hipEventCreate(&ev) == hipSuccess;
-  float t1 = 0.f, t2 = 0.f;
+  for (int i = 0; i <= 2 * m; ++i) ok = ok && hipEventCreate(&e[i]) == hipSuccess;
+  float best_t[3] = {0.f, 0.f, 0.f};
   if (ok) {
     ok = hipEventRecord(e[0], c->st) == hipSuccess;
-    for (int r = 0; r < 4 && ok; ++r)
-      ok = launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym, c->bnorm, 1 + (r & 1)) &&
+    for (int r = 0; r < 2 * m && ok; ++r)
+      ok = launch_phase2_mfma(c->st, c->prm.metric, c->mprec, c->DM, A, c->mu, c->Ym, c->bnorm, ids[r % m]) &&
            hipEventRecord(e[r + 1], c->st) == hipSuccess;
-    float dt[4] = {0.f, 0.f, 0.f, 0.f};
-    ok = ok && hipEventSynchronize(e[4]) == hipSuccess;
-    for (int r = 0; r < 4 && ok; ++r) ok = hipEventElapsedTime(&dt[r], e[r], e[r + 1]) == hipSuccess;
-    t1 = dt[0] < dt[2] ? dt[0] : dt[2];
-    t2 = dt[1] < dt[3] ? dt[1] : dt[3];
+    ok = ok && hipEventSynchronize(e[2 * m]) == hipSuccess;
+    for (int r = 0; r < 2 * m && ok; ++r) {
+      float dt = 0.f;
+      ok = hipEventElapsedTime(&dt, e[r], e[r + 1]) == hipSuccess;
+      if (r < m || dt < best_t[r % m]) best_t[r % m] = dt;
+    }
   }
   for (auto& ev : e)
     if (ev) (void)hipEventDestroy(ev);
@@ -852,7 +860,13 @@ int pick_pb(silh_ctx* c, const P2Args& A) {
     (void)hipGetLastError();
     return pb_builtin(c->prm.metric, c->mprec, c->DM);
   }
-  const int choice = t2 < t1 ? 2 : 1;
+  int choice = ids[0];
+  float tb = best_t[0];
+  for (int i = 1; i < m; ++i)
+    if (best_t[i] < tb) {
+      tb = best_t[i];
+      choice = ids[i];
+    }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.emplace(key, choice);
   return choice;
@@ -1003,6 +1017,83 @@ silh_status validate_exact_params(const silh_params* prm, const float* X, const 
 }
 int dm_for(int d) { return phase2_valu_dm(d); }
 silh_status set_error(silh_status st, const char* msg) { return fail(st, "%s", msg); }
+int64_t sample_rows(const silh_ctx* c) { return c && c->state == 1 ? c->S_pad : 0; }
+
+int tuned_shape(silh_ctx* c) {
+  if (!c || c->state != 1 || !c->mfma) return 1;
+  P2Args A;
+  A.X = c->X;
+  A.n = c->n;
+  A.d = c->d;
+  A.labels = c->labels;
+  A.Y = c->Y32;
+  A.w = c->w32;
+  A.aux = c->aux32;
+  A.gid_pk = c->gid_pk;
+  A.sp_off = c->sp_off;
+  A.cnt = c->cnt;
+  A.csize = c->csize;
+  A.k = c->k;
+  A.a = A.b = A.s = A.What = nullptr;
+  A.bpart = c->bpart;
+  A.rn = c->rn;
+  return pick_pb(c, A);
+}
+
+bool phase2_job(silh_ctx* c, P2Job* job, P2Class* cls) {
+  if (!c || c->state != 1) return false;
+  const bool batch = c->mfma || phase2_valu_jobs_ok(c->prm.metric, c->DM);
+  if (!batch) return false;
+  P2Job J{};
+  J.X = c->X;
+  J.labels = c->labels;
+  J.Ym = c->Ym;
+  J.w = c->w32;
+  J.gid_pk = c->gid_pk;
+  J.sp_off = c->sp_off;
+  J.cnt = c->cnt;
+  J.csize = c->csize;
+  J.mu = c->mu;
+  J.a = J.b = J.s = J.What = nullptr;
+  J.bpart = c->bpart;
+  J.bnorm = c->bnorm;
+  J.Y32 = c->Y32;
+  J.aux = c->aux32;
+  J.rn = c->rn;
+  J.n = c->n;
+  J.d = c->d;
+  J.k = c->k;
+  *job = J;
+  P2Class K{};
+  K.mfma = c->mfma ? 1 : 0;
+  K.metric = c->prm.metric;
+  K.prec = c->mfma ? c->mprec : -1;
+  K.DM = c->DM;
+  K.pb = c->mfma ? tuned_shape(c) : 1;
+  K.rows = c->mfma ? phase2_mfma_rows(c->mprec, c->DM) * (K.pb == 2 ? 2 : 1) : c->p2_rows;
+  K.blocks = ceil_div(c->n, K.rows);
+  K.S_pad = c->S_pad;
+  *cls = K;
+  return true;
+}
+
+bool launch_phase2_class(hipStream_t st, const P2Class& cls, const P2Job* jobs, const int2* items, int nitems) {
+  if (cls.mfma) return launch_phase2_mfma_jobs(st, cls.metric, cls.prec, cls.DM, cls.pb, jobs, items, nitems);
+  return launch_phase2_valu_jobs(st, cls.metric, cls.DM, jobs, items, nitems);
+}
+
+silh_status phase2_job_mean(silh_ctx* c, double* mean) {
+  if (!c || c->state != 1) return fail(SILH_E_STATE, "no sampled context");
+  {
+    Launch L(c, K_MEAN);
+    launch_mean(c->st, c->bpart, (int)ceil_div(c->n, c->p2_rows), c->n, c->mean_d);
+    CHK(L.done());
+  }
+  CHK(fetch(c, {{&c->mean_h, c->mean_d, sizeof(double)}}));
+  *mean = c->mean_h;
+  return SILH_OK;
+}
+
 int pb_builtin(int metric, int prec, int DM) {
   if (metric == SILH_COS && prec == 1 && DM == 32) return 2;
   return mfma_pb_default(prec, DM);
@@ -1147,7 +1238,7 @@ silh_status silh_coh_sep(silh_ctx* c, const float* W_hat, double* coh_host, doub
 }
 
 silh_status silh_set_tuning(int mode) {
-  if (mode < 0 || mode > 3) return fail(SILH_E_ARG, "tuning mode %d outside [0, 3]", mode);
+  if (mode < 0 || mode > 4) return fail(SILH_E_ARG, "tuning mode %d outside [0, 4]", mode);
   g_tune_mode.store(mode);
   if (mode == 1) {
     std::lock_guard<std::mutex> lk(g_tune_mu);

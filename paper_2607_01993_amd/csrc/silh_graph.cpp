@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -58,6 +59,8 @@ struct silh_graph {
   const int32_t* labels = nullptr;
   std::vector<int32_t> ks;
   std::vector<int64_t> ts;  // Algorithm 1's t of each clustering (k enters it when derived from eps)
+  std::vector<int32_t> shape;    // Phase-2 block shape captured for each clustering
+  std::vector<int64_t> probe_S;  // padded sample size of the request the shape was tuned on
   int K = 0, n = 0, d = 0, DM = 0, KP = 0, mprec = 0, p2_rows = 0, chunk = 0, kmax = 0;
   bool mfma = false;
   int64_t S_cap = 0, F0_cap = 0, items_cap = 0, part_cap = 0, dist_cap = 0;
@@ -224,7 +227,7 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
     if (!launch_pack_mfma(st, metric, g->mprec, DM, b.Y32, b.aux32, b.sp_off, b.cnt, k, b.mu, (int)g->S_cap, b.Ym,
                           b.bnorm))
       return false;
-    if (!launch_phase2_mfma(st, metric, g->mprec, DM, A, b.mu, b.Ym, b.bnorm, pb_builtin(metric, g->mprec, DM)))
+    if (!launch_phase2_mfma(st, metric, g->mprec, DM, A, b.mu, b.Ym, b.bnorm, g->shape[(size_t)i]))
       return false;
   } else if (!launch_phase2_valu(st, metric, DM, A)) {
     return false;
@@ -321,6 +324,35 @@ silh_status silh_graph_create(const silh_params* base, const float* X, const int
     release(g);
     return set_error(SILH_E_HIP, "stream, event or pinned allocation failed");
   }
+  // Phase-2 block shapes from the autotuner: one eager request per group of
+  // clusterings with the same floor(log2(k t)) (the padded sample size is
+  // the tuner's key), tuned on its real sample; a probe that fails (bad
+  // labels, ...) leaves the built-in shape
+  g->shape.assign((size_t)K, 1);
+  g->probe_S.assign((size_t)K, 0);
+  if (g->mfma) {
+    std::map<int, std::pair<int32_t, int64_t>> group;
+    for (int32_t i = 0; i < K; ++i) {
+      const double kt = (double)ks[i] * (double)ts[(size_t)i];
+      const int gk = (int)std::floor(std::log2(kt > 1.0 ? kt : 1.0));
+      auto it = group.find(gk);
+      if (it == group.end()) {
+        silh_params prm = *base;
+        prm.k = ks[i];
+        silh_ctx* c = nullptr;
+        std::pair<int32_t, int64_t> pick{pb_builtin(base->metric, g->mprec, g->DM), 0};
+        if (silh_sample_init(&prm, X, labels + (size_t)i * (size_t)g->n, stream, &c) == SILH_OK &&
+            silh_pps_sample(c, nullptr, nullptr) == SILH_OK) {
+          pick = {tuned_shape(c), sample_rows(c)};
+        }
+        silh_destroy(c);
+        it = group.emplace(gk, pick).first;
+      }
+      g->shape[(size_t)i] = it->second.first;
+      g->probe_S[(size_t)i] = it->second.second;
+    }
+    (void)hipGetLastError();
+  }
   // capture: fork every branch from the capture stream, enqueue, join back
   bool built = hipStreamBeginCapture(g->cap_st, hipStreamCaptureModeThreadLocal) == hipSuccess;
   bool captured = built;
@@ -393,6 +425,14 @@ silh_status silh_graph_get_info(const silh_graph* g, silh_graph_info* out) {
   out->sample_cap = g->S_cap;
   out->f0_cap = g->F0_cap;
   out->bytes = g->bytes;
+  return SILH_OK;
+}
+
+silh_status silh_graph_choice(const silh_graph* g, int32_t i, int32_t* shape, int64_t* probe_S_pad) {
+  if (!g || !shape || !probe_S_pad) return set_error(SILH_E_ARG, "NULL argument");
+  if (i < 0 || i >= g->K) return set_error(SILH_E_ARG, "clustering index outside [0, K)");
+  *shape = g->shape[(size_t)i];
+  *probe_S_pad = g->probe_S[(size_t)i];
   return SILH_OK;
 }
 

@@ -134,7 +134,7 @@ bool launch_phase2_valu(hipStream_t st, int metric, int DM, const P2Args& a);
 // are phase2_valu_rows / phase2_mfma_rows * pb elements.
 bool launch_phase2_valu_jobs(hipStream_t st, int metric, int DM, const P2Job* jobs, const int2* items, int nitems);
 bool phase2_valu_jobs_ok(int metric, int DM);
-bool launch_phase2_mfma_jobs(hipStream_t st, int metric, int prec, int DM, int pb, const P2Job* jobs,
+bool launch_phase2_mfma_jobs(hipStream_t st, int metric, int prec, int DM, int shape, const P2Job* jobs,
                              const int2* items, int nitems);
 int phase2_valu_dm(int d);   // padded dimension used by the VALU kernel, 0 if unsupported
 // elements per block (and per partial of the mean) of the VALU kernel
@@ -156,15 +156,19 @@ bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float*
 // elements per float64 partial of the sum of s_hat written by the MFMA
 // Phase-2 kernel (independent of its block shape)
 int phase2_mfma_rows(int prec, int DM);
-// 32-element blocks per wave: the default choice, and the launcher (pb 1 or
-// 2; fp8 always runs with 1)
+// Block shapes (ids): 1 one 32-element block per wave, 2 two blocks per wave
+// (d <= 64, not fp8), 3 one block with the other number of tiles per LDS
+// stage (the LDS-staged shapes only).  The default choice of blocks per wave:
 int mfma_pb_default(int prec, int DM);
-// the built-in block shape with the metric taken into account (cosine bf16
-// at d = 32 measures faster with two blocks per wave, Euclidean with one)
+// the built-in shape with the metric taken into account (cosine bf16 at
+// d = 32 measures faster with two blocks per wave, Euclidean with one)
 int pb_builtin(int metric, int prec, int DM);
 int mfma_pb_max(int prec, int DM);
+bool mfma_lds_path(int prec, int DM);
+// the shape ids valid for (prec, DM) into ids[0..2]; returns their count
+int mfma_shapes(int prec, int DM, int* ids);
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,
-                        const void* Ym, const float* bnorm, int pb);
+                        const void* Ym, const float* bnorm, int shape);
 
 // ---- global mean -------------------------------------------------------------
 void launch_mean(hipStream_t st, const double* bpart, int nb, int64_t n, double* out);
@@ -211,6 +215,30 @@ silh_status validate_exact_params(const silh_params* prm, const float* X, const 
 int dm_for(int d);
 // sets the thread's silh_last_error message and returns st
 silh_status set_error(silh_status st, const char* msg);
+
+// ---- one request's Phase 2 inside a multi-request launch (serving) ---------
+// The kernel class of a request's Phase 2 (requests of one class share a
+// launch) and its work: `blocks` work items of `rows` elements, each against
+// the S_pad packed sample rows.
+struct P2Class {
+  int mfma, metric, prec, DM, pb, rows;  // prec: 0 float32, 1 bf16, 2 fp8 operands, -1 vector ALU; pb: shape id
+  int64_t blocks, S_pad;
+};
+// After a successful silh_pps_sample: ctx's Phase 2 (no per-element outputs;
+// the block partials of the mean stay in the context) as a job of the
+// multi-request launch.  False when its shape has no multi-request kernel
+// (vector ALU with d > 128): then silh_scores runs it alone.
+bool phase2_job(silh_ctx* c, P2Job* job, P2Class* cls);
+// the autotuner's shape for ctx's Phase 2 (timing the shapes on ctx's data
+// when its key is new; the built-in shape on the vector ALUs or in mode 0)
+int tuned_shape(silh_ctx* c);
+// padded sample rows of a sampled context (the tuner's size key), else 0
+int64_t sample_rows(const silh_ctx* c);
+// launch work items of requests of one class (workgroup i runs items[i])
+bool launch_phase2_class(hipStream_t st, const P2Class& cls, const P2Job* jobs, const int2* items, int nitems);
+// after the job's items have all run: the Eq. 9 mean from its block partials
+// (on the context's stream; synchronises it)
+silh_status phase2_job_mean(silh_ctx* c, double* mean);
 
 // ---- cohesion / separation numerators from W_hat [n][k] ---------------------
 constexpr int kCohSepMaxBlocks = 1024;

@@ -40,7 +40,7 @@ class SilhSampleInfo(ctypes.Structure):
 
 
 class SilhServerCfg(ctypes.Structure):
-    _fields_ = [("workers", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+    _fields_ = [("workers", ctypes.c_int32), ("mode", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
 
 
 class SilhRequest(ctypes.Structure):
@@ -102,6 +102,7 @@ SIGNATURES = {
     "silh_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(SilhResult)]),
     "silh_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
     "silh_server_destroy": (None, [ctypes.c_void_p]),
+    "silh_server_launches": (ctypes.c_int64, [ctypes.c_void_p]),
     "silh_sweep": (ctypes.c_int, [ctypes.POINTER(SilhParams), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                   ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -113,6 +114,8 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]),
     "silh_graph_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "silh_graph_choice": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64)]),
     "silh_graph_destroy": (None, [ctypes.c_void_p]),
     "silh_last_error": (ctypes.c_char_p, []),
     "silh_version": (ctypes.c_char_p, []),
@@ -458,8 +461,9 @@ def gl_pps_s(X, labels, k, m, t, seed, rows_seed, metric="eucl", prec="fp32", sa
 
 
 def silh_set_tuning(mode):
-    """0 built-in block shape, 1 autotune (default), 2 / 3 force one / two
-    32-element blocks per wave (matrix-core Phase 2)."""
+    """0 built-in block shape, 1 autotune (default), 2 / 3 / 4 force shape 1
+    (one 32-element block per wave), 2 (two blocks) or 3 (one block, the
+    other number of tiles per LDS stage) of the matrix-core Phase 2."""
     _check(load_library().silh_set_tuning(int(mode)), "silh_set_tuning")
 
 
@@ -617,6 +621,13 @@ class SweepGraph:
                 "status": [STATUS.get(int(v), int(v)) for v in status], "best": int(best.value),
                 "reruns": int(reruns.value)}
 
+    def choice(self, i):
+        """(shape id captured for clustering i, padded sample size it was tuned on)"""
+        shape, S = ctypes.c_int32(), ctypes.c_int64()
+        _check(load_library().silh_graph_choice(self.ptr, int(i), ctypes.byref(shape), ctypes.byref(S)),
+               "silh_graph_choice")
+        return int(shape.value), int(S.value)
+
     def info(self):
         out = SilhGraphInfo()
         _check(load_library().silh_graph_get_info(self.ptr, ctypes.byref(out)), "silh_graph_get_info")
@@ -641,10 +652,10 @@ class Server:
     """Resident datasets, a request queue with a device-memory budget, and
     worker threads with their own streams (all in the HIP library)."""
 
-    def __init__(self, workers=4, hbm_budget_bytes=64 << 30):
+    def __init__(self, workers=4, hbm_budget_bytes=64 << 30, batched=True):
         _torch()
         lib = load_library()
-        cfg = SilhServerCfg(int(workers), 0, int(hbm_budget_bytes))
+        cfg = SilhServerCfg(int(workers), 0 if batched else 1, int(hbm_budget_bytes))
         out = ctypes.c_void_p()
         _check(lib.silh_server_create(ctypes.byref(cfg), ctypes.byref(out)), "silh_server_create")
         self.ptr = out
@@ -686,6 +697,10 @@ class Server:
 
     def drain(self):
         _check(load_library().silh_server_drain(self.ptr), "silh_server_drain")
+
+    def launches(self):
+        """Shared Phase-2 launches issued so far."""
+        return int(load_library().silh_server_launches(self.ptr))
 
     @staticmethod
     def now_ns():

@@ -132,7 +132,7 @@ def test_server_layouts_and_argument_checks():
     assert ctypes.sizeof(P.SilhResult) == 48 + 160
     lib = native.load_library()
     out = ctypes.c_void_p()
-    for w, r, b in ((0, 0, 1 << 30), (65, 0, 1 << 30), (2, 1, 1 << 30), (2, 0, 0)):
+    for w, r, b in ((0, 0, 1 << 30), (65, 0, 1 << 30), (2, 2, 1 << 30), (2, -1, 1 << 30), (2, 0, 0)):
         cfg = P.SilhServerCfg(w, r, b)
         assert lib.silh_server_create(ctypes.byref(cfg), ctypes.byref(out)) == 1
         assert not out.value
@@ -142,6 +142,7 @@ def test_server_layouts_and_argument_checks():
     assert lib.silh_server_drain(None) == 1
     assert lib.silh_server_add_dataset(None, None, 10, 4, None) == 1
     lib.silh_server_destroy(None)
+    assert lib.silh_server_launches(None) == -1
     t0 = lib.silh_server_now_ns()
     assert lib.silh_server_now_ns() >= t0 > 0
 
@@ -162,6 +163,8 @@ def test_graph_layout_and_argument_checks():
     assert not out.value
     assert lib.silh_graph_run(None, None, None, None, None, None) == 1
     assert lib.silh_graph_get_info(None, None) == 1
+    shape, S = ctypes.c_int32(), ctypes.c_int64()
+    assert lib.silh_graph_choice(None, 0, ctypes.byref(shape), ctypes.byref(S)) == 1
     lib.silh_graph_destroy(None)
 
 

@@ -36,17 +36,21 @@ REQS = [  # (dataset, metric, prec, sampler, t, seed)
 ]
 
 
-@pytest.mark.parametrize("workers", [1, 3])
-def test_server_results_equal_direct_calls(workers):
+@pytest.mark.parametrize("workers,batched", [(1, True), (3, True), (3, False)])
+def test_server_results_equal_direct_calls(workers, batched):
+    """Each request's mean, served in the mix (Phase 2 in shared launches
+    when batched), equals the same request run alone, bit for bit."""
     ds = _datasets()
-    srv = native.Server(workers=workers, hbm_budget_bytes=8 << 30)
+    srv = native.Server(workers=workers, hbm_budget_bytes=8 << 30, batched=batched)
     ids = [srv.add_dataset(X) for X, _, _ in ds]
     tickets = []
     for (di, metric, prec, sampler, t, seed) in REQS:
         X, L, k = ds[di]
         tickets.append(srv.submit(ids[di], L, k, metric, prec, sampler, t=t, seed=seed))
     results = [srv.wait(tk) for tk in tickets]
+    launches = srv.launches()
     srv.close()
+    assert (launches >= 1) if batched else (launches == 0)
     for (di, metric, prec, sampler, t, seed), res in zip(REQS, results):
         X, L, k = ds[di]
         assert res["status"] == "SILH_OK", res
@@ -108,3 +112,56 @@ def test_server_checks_requests_and_reports_failures():
         srv.wait(tb)                # retired
     srv.drain()
     srv.close()
+
+
+def test_served_means_against_the_oracle():
+    """Requests served together (shared Phase-2 launches) against the float64
+    oracle's Eq. 9 mean: float32 within 4e-5, bf16 / fp8 within 1e-3."""
+    import oracle
+    ds = _datasets()
+    host = [(X.cpu().numpy(), L.cpu().numpy(), k) for X, L, k in ds]
+    srv = native.Server(workers=2, hbm_budget_bytes=8 << 30)
+    ids = [srv.add_dataset(X) for X, _, _ in ds]
+    picks = [REQS[i] for i in (0, 1, 2, 3, 5, 8, 10)]
+    tickets = [srv.submit(ids[di], ds[di][1], ds[di][2], metric, prec, sampler, t=t, seed=seed)
+               for (di, metric, prec, sampler, t, seed) in picks]
+    results = [srv.wait(tk) for tk in tickets]
+    srv.close()
+    for (di, metric, prec, sampler, t, seed), res in zip(picks, results):
+        Xh, Lh, k = host[di]
+        ref = oracle.pps_silhouette(Xh, Lh, k, metric, t=t, delta=0.01, seed=seed, sampler=sampler)
+        bar = 4e-5 if prec in ("fp32", "fp32_valu") else 1e-3
+        print(f"{metric}/{prec}: served {res['s_mean']:.8f} oracle {ref['mean']:.8f}")
+        assert res["status"] == "SILH_OK"
+        assert res["S"] == sum(f.shape[0] for f in ref["sample"]["F"])
+        assert abs(res["s_mean"] - ref["mean"]) <= bar
+
+
+def test_small_requests_are_not_held_behind_a_large_one():
+    """A large Canberra request (seconds of Phase 2 on the vector ALUs), then
+    small Euclidean ones: every small request completes before the large one,
+    and a d = 256 Manhattan request (its own launch) in the mix is served too."""
+    Xb, Lb = synth.tiny_case(1_000_000, 32, 64, seed=71)
+    Xb = np.abs(Xb) + 0.5
+    Xs, Ls = synth.tiny_case(20_000, 16, 8, seed=72)
+    Xw, Lw = synth.tiny_case(3_000, 256, 3, seed=73)
+    big = (torch.from_numpy(Xb).cuda(), torch.from_numpy(Lb).cuda())
+    small = (torch.from_numpy(Xs).cuda(), torch.from_numpy(Ls).cuda())
+    wide = (torch.from_numpy(Xw).cuda(), torch.from_numpy(Lw).cuda())
+    srv = native.Server(workers=4, hbm_budget_bytes=32 << 30)
+    ib, is_, iw = srv.add_dataset(big[0]), srv.add_dataset(small[0]), srv.add_dataset(wide[0])
+    tb = srv.submit(ib, big[1], 64, "canb", "fp32", t=1024, seed=1)
+    ts = [srv.submit(is_, small[1], 8, "eucl", "bf16", t=64, seed=10 + i) for i in range(8)]
+    tw = srv.submit(iw, wide[1], 3, "manh", "fp32", t=64, seed=3)
+    rb = srv.wait(tb)
+    rs = [srv.wait(t) for t in ts]
+    rw = srv.wait(tw)
+    srv.close()
+    assert rb["status"] == "SILH_OK" and rw["status"] == "SILH_OK"
+    assert all(r["status"] == "SILH_OK" for r in rs)
+    big_ms = (rb["done_ns"] - rb["submit_ns"]) / 1e6
+    small_ms = [(r["done_ns"] - r["submit_ns"]) / 1e6 for r in rs]
+    print(f"large request {big_ms:.1f} ms; small requests max {max(small_ms):.1f} ms")
+    assert all(r["done_ns"] < rb["done_ns"] for r in rs)
+    S, mean = _direct(wide[0], wide[1], 3, "manh", "fp32", "pps", 64, 3)
+    assert rw["s_mean"] == mean and rw["S"] == S
