@@ -83,12 +83,26 @@ struct MCfg {
   static constexpr int HALF = KP / 2;
   static constexpr int NSTEP = P == 0 ? HALF : (P == 1 ? HALF / 8 : HALF / 32);
   static constexpr int ELEM = P == 0 ? 4 : (P == 1 ? 2 : 1);  // operand bytes
+  // long rows go through LDS (the block's waves share each tile)
+  static constexpr bool LDS = P == 2 ? HALF > 40 : HALF > 30;
+  // bytes per packed row: the operands, and on the LDS path a 16-byte tail
+  // with the sample's weight and per-sample value (so that one contiguous
+  // copy brings a whole tile into LDS)
+  static constexpr int ROWB = KP * ELEM + (LDS ? 16 : 0);
 };
 
 int mfma_kp(int prec, int DM) {
   if (prec == 0) return round_up_c(DM + 2, 4);
   if (prec == 1) return round_up_c(DM + 6, 16);
   return round_up_c(DM, 64);
+}
+
+bool mfma_lds_path(int prec, int DM) {
+  return prec == 2 ? round_up_c(DM, 64) / 2 > 40 : mfma_kp(prec, DM) / 2 > 30;
+}
+
+int mfma_row_bytes(int prec, int DM) {
+  return mfma_kp(prec, DM) * (prec == 0 ? 4 : (prec == 1 ? 2 : 1)) + (mfma_lds_path(prec, DM) ? 16 : 0);
 }
 
 __device__ __forceinline__ int fp8_pack4(float a, float b, float c, float d) {
@@ -151,11 +165,15 @@ void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32
 // B operand rows: [ -2 alpha y~_q (DM) | augmentation | 0 ... ] with
 // alpha = 1 (Euclidean) or 1/2 (cosine); y~_q = y~ rounded to the input
 // precision; the augmentation carries alpha |y~_q|^2 + u_y.  Padding rows are
-// all zero.
+// all zero.  On the LDS path each row ends in 16 bytes: the weight w, the
+// per-sample value (Euclidean: the recompute threshold; fp8: the norm term;
+// cosine: the element id), two zero words.
 // ----------------------------------------------------------------------------
 template <int M, int P, int DM>
 __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32,
                                                    const float* __restrict__ aux,
+                                                   const float* __restrict__ w,
+                                                   const int32_t* __restrict__ gid_pk,
                                                    const int32_t* __restrict__ sp_off,
                                                    const int32_t* __restrict__ cnt, int k,
                                                    const float* __restrict__ mu, int S_pad,
@@ -192,9 +210,11 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
     }
     bnorm[s] = bn;
-    int* out = (int*)((unsigned char*)Ym + (size_t)s * C::KP);
+    int* out = (int*)((unsigned char*)Ym + (size_t)s * C::ROWB);
 #pragma unroll
     for (int c = 0; c < C::KP; c += 4) out[c / 4] = fp8_pack4(row[c], row[c + 1], row[c + 2], row[c + 3]);
+    if constexpr (C::LDS)
+      *(u32x4*)(out + C::KP / 4) = u32x4{__float_as_uint(w[s]), __float_as_uint(bn), 0u, 0u};
     return;
   }
   float thr = 0.0f;
@@ -220,14 +240,19 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
     }
   }
   bnorm[s] = thr;
+  unsigned char* rowp = (unsigned char*)Ym + (size_t)s * C::ROWB;
   if constexpr (P == 0) {
-    float* out = (float*)Ym + (size_t)s * C::KP;
+    float* out = (float*)rowp;
 #pragma unroll
     for (int c = 0; c < C::KP; ++c) out[c] = row[c];
   } else {
-    __bf16* out = (__bf16*)Ym + (size_t)s * C::KP;
+    __bf16* out = (__bf16*)rowp;
 #pragma unroll
     for (int c = 0; c < C::KP; ++c) out[c] = (__bf16)row[c];
+  }
+  if constexpr (C::LDS) {
+    const unsigned g = M == kCos ? (unsigned)gid_pk[s] : __float_as_uint(thr);
+    *(u32x4*)(rowp + C::KP * C::ELEM) = u32x4{__float_as_uint(w[s]), g, 0u, 0u};
   }
 }
 
@@ -324,6 +349,38 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, int byt
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
 }
 
+// 16 bytes per lane at byte voff + soff of the buffer straight into LDS:
+// lane l's bytes land at LDS byte address la + 16 l (la, the descriptor and
+// soff wave-uniform).  Written as one asm statement (M0, the LDS address, saved
+// and restored around it) because the compiler, unable to tell the slot being
+// filled from the slots being read, would otherwise wait for every such load
+// before the next LDS read; the kernel orders them itself (a vmcnt wait and a
+// barrier before a slot is read, no load into a slot read in the same stage).
+// It has no register results, so nothing the compiler allocates is written
+// late.
+__device__ __forceinline__ void lds_load16(u32x4 rsrc, unsigned la, unsigned voff, unsigned soff) {
+  // all wave-uniform; made explicit for the scalar operands of the asm
+  la = (unsigned)__builtin_amdgcn_readfirstlane((int)la);
+  rsrc = u32x4{(unsigned)__builtin_amdgcn_readfirstlane((int)rsrc.x), (unsigned)__builtin_amdgcn_readfirstlane((int)rsrc.y),
+               (unsigned)__builtin_amdgcn_readfirstlane((int)rsrc.z), (unsigned)__builtin_amdgcn_readfirstlane((int)rsrc.w)};
+  unsigned saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "buffer_load_dwordx4 %2, %3, 0 offen lds\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(la), "v"(voff + soff), "s"(rsrc)
+      : "memory");
+}
+
+// the buffer descriptor of lds_load16: `bytes` bytes from p (stride 0; reads
+// past the end give 0)
+__device__ __forceinline__ u32x4 rsrc_words(const void* p, unsigned bytes) {
+  const unsigned long long a = (unsigned long long)(uintptr_t)p;
+  return u32x4{(unsigned)a, (unsigned)(a >> 32) & 0xffffu, bytes, 0x00020000u};
+}
+
 // V consecutive row elements from c on, zero from lim on.  With vec (rows
 // V-float aligned and c a multiple of V) the chunk is one vector load and lies
 // wholly inside or outside [0, lim); otherwise element by element.  Loads go
@@ -385,17 +442,19 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
 
 // waves per SIMD the one-block shapes from d = 32 on keep (their occupancy
 // without the recompute path, which must not lower it)
-template <int M, int P, int DM, int PB>
-constexpr int kMinWaves = (M != kEucl || P == 2 || PB == 2 || DM < 32) ? 1
+// (two tiles per LDS stage hold enough LDS to set the occupancy themselves)
+template <int M, int P, int DM, int PB, int TBX>
+constexpr int kMinWaves = (M != kEucl || P == 2 || PB == 2 || DM < 32 || (TBX == 2 && MCfg<P, DM>::LDS)) ? 1
                           : DM == 32 ? (P == 1 ? 4 : 1) : DM == 64 ? 3 : DM == 128 ? 2 : 1;
 
 // One block of the Phase-2 launch: 4 waves x PB x 32 elements, from element
 // blk * 128 * PB on.  The kernels below run it for blockIdx.x (one request)
 // or for the (request, block) work items of a multi-request launch.
+
 // tiles per LDS stage of the one-block shape by default: two where measured
-// faster (bf16 at d = 64, fp8), else one; the autotuner may try the other
+// faster (bf16 from d = 64 on, fp8), else one; the autotuner may try the other
 template <int P, int DM>
-constexpr int kTBDefault = (P == 2 || (P == 1 && DM == 64)) ? 2 : 1;
+constexpr int kTBDefault = (P == 2 || (P == 1 && DM >= 64)) ? 2 : 1;
 
 template <int M, int P, int DM, int PB, int TBX>
 __device__ __forceinline__ void p2_mfma_block(
@@ -412,25 +471,35 @@ __device__ __forceinline__ void p2_mfma_block(
   static_assert(C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
   constexpr float S2 = kFp8Scale * kFp8Scale;
   __shared__ double sh32[4 * PB];  // 32-element partials of the block, in element order
-  // long rows (bf16 / float32 with d >= 64, fp8 with d >= 128): LDS tiles of
-  // 32 packed rows shared by the block's waves, rows padded by 16 bytes so
-  // that the lanes' 16-byte reads fall in different banks
+  // Long rows (bf16 / float32 with d >= 64, fp8 with d >= 128): the block's
+  // four waves sweep the same tiles, so each is loaded once per block into
+  // LDS and every wave reads its B fragment from there.  Tiles go in stages
+  // of kTB; a stage's slot holds its tiles (32 packed rows each, whose
+  // 16-byte tails with the weight and per-sample value also shift the rows
+  // so that the lanes' 16-byte reads fall in different banks; the tile
+  // padded to whole kilobytes) and the centre mu_j of the stage's cluster.  Slots are filled by direct
+  // global-to-LDS loads (16 bytes per lane, placed at the slot offset plus
+  // 16 x lane) two stages ahead in a ring of three, so a stage's loads have
+  // two stages of compute to arrive; one wait and one barrier per stage.
   constexpr int kRowB = C::KP * C::ELEM;
-  constexpr int kLRow = kRowB + 16;
-  constexpr int kTileB = 32 * kLRow;
-  constexpr int kChRow = kRowB / 16;
-  constexpr int kNCh = 32 * kChRow;
-  constexpr int kPer = (kNCh + 255) / 256;
-  constexpr bool kLds = P == 2 ? C::HALF > 40 : C::HALF > 30;
-  // tiles per LDS stage (one barrier per stage): two where it costs no wave
-  // per SIMD and measured faster (bf16 at d = 64, fp8), else one
+  constexpr int kLRow = C::ROWB;                    // operands + tail (weight, value)
+  constexpr int kTileCh = round_up_c(32 * kLRow / 16, 64);
+  constexpr int kTileI = kTileCh / 64;              // loads (one per wave) per tile
+  constexpr bool kLds = C::LDS;
+  // tiles per LDS stage (one barrier per stage; kTBDefault or the other)
   constexpr int kTB = (kLds && PB == 1) ? TBX : 1;
-  __shared__ __attribute__((aligned(16))) unsigned char ldsB[kLds ? 2 * kTB * kTileB : 16];
-  __shared__ float ldsW[2][kTB * 32];
-  __shared__ int ldsG[2][kTB * 32];
-  u32x4 stage[kTB][kLds ? kPer : 1];
-  float sw[kTB] = {};
-  int sg[kTB] = {};
+  constexpr int kMuOff = kTB * kTileCh * 16;
+  constexpr int kMuI = (C::KP * 4 + 1023) / 1024;   // loads for mu (its region: whole kilobytes)
+  constexpr int kSlotB = kMuOff + kMuI * 1024;
+  static_assert(!kLds || (kTileI >= 4 && kMuI <= 4), "every wave loads part of each tile; mu takes at most four loads");
+  constexpr int kDw = (kTileI + 3) / 4;             // loads per wave per tile
+  constexpr int kNIw = kTB * kDw;                   // per wave per stage, without mu
+  // LDS path with bf16 / fp8 operands: one tile's epilogue runs beside the
+  // next tile's MFMAs (float32 operands are bound by the MFMA rate)
+  constexpr bool kPipe = kLds && P != 0 && DM >= 128;
+  __shared__ __attribute__((aligned(16))) unsigned char ldsS[kLds ? 3 * kSlotB : 16];
+  // the LDS byte address of ldsS (the direct loads take LDS addresses)
+  const unsigned lds_base = (unsigned)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)ldsS;
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int col = lane & 31;
@@ -451,6 +520,18 @@ __device__ __forceinline__ void p2_mfma_block(
   typedef float fvec __attribute__((ext_vector_type(V)));
   const bool vec = d % V == 0 && ((uintptr_t)X & (4 * V - 1)) == 0;
   float xr[PB][C::HALF];
+  // d = 256: the rows wait in the AGPRs, so the vector registers serve the
+  // tile pipeline (deeper B-operand reads ahead of the MFMAs)
+  constexpr bool kXA = kLds && C::HALF >= 128;
+  auto xget = [&](int b, int i) {
+    if constexpr (kXA) {
+      float r;
+      asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(r) : "a"(xr[b][i]));
+      return r;
+    } else {
+      return xr[b][i];
+    }
+  };
   float ux[PB];
   int pout[PB], own[PB];
   double w_own[PB], bmin[PB];
@@ -475,6 +556,12 @@ __device__ __forceinline__ void p2_mfma_block(
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
     }
+    if constexpr (kXA) {
+      // kept in accumulation registers (AGPRs) until the A operands of each
+      // cluster read them back
+#pragma unroll
+      for (int i = 0; i < C::HALF; ++i) asm volatile("v_accvgpr_write_b32 %0, %1" : "=a"(xr[b][i]) : "v"(xr[b][i]));
+    }
     pout[b] = P0 + 32 * b + prow;
     own[b] = labels[pout[b] < n ? pout[b] : n - 1];
     own[b] = (unsigned)own[b] < (unsigned)k ? own[b] : 0;  // labels are checked before; stay in bounds
@@ -492,14 +579,82 @@ __device__ __forceinline__ void p2_mfma_block(
   // register path) or in LDS buffer `cb` (the LDS path).
   const int last_row = sp_off[k] - 32;
   auto clamp_row = [&](int row) { return row <= last_row ? row : last_row; };
-  int pre = -1, cb = 0;
+  int pre = -1;
   BFrag<P, DM> b0, b1;
   float w0 = 0.f, w1 = 0.f;
   int g0 = -1, g1 = -1;
+
+  // ---- LDS path: the stage ring.  (cj, cm) is the next stage to load
+  // (cluster, stage within it; cj = k past the end, where the last tile is
+  // loaded again and never read); rs the slot of the next stage to compute.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int cj = 0, cm = 0, rs = 0;
+  int cnt_c = 0, row_c = 0;  // samples and first packed row of cluster cj
+  auto seek = [&](int j0) {  // cj: the first cluster from j0 on with samples
+    while (j0 < k && cnt[j0] <= 0) ++j0;
+    cj = j0;
+    if (j0 < k) {
+      cnt_c = cnt[j0];
+      row_c = sp_off[j0];
+    }
+  };
+  auto advance = [&]() {
+    if (cj >= k) return;
+    if (++cm * kTB * 32 >= cnt_c) {
+      cm = 0;
+      seek(cj + 1);
+    }
+  };
+  // Wave w loads kilobytes w, w + 4, ... of each tile (kDw loads; where the
+  // tile ends first the last one repeats its final kilobyte, the same bytes
+  // to the same place, so every wave issues the same count) and kilobyte w
+  // of mu.  stage_begin fixes the stage to load next and loads its mu;
+  // tile_load(tt, mi) issues load mi of its tile tt.
+  const unsigned voff0 = 16u * (unsigned)lane;
+  int st_row0 = 0;
+  unsigned st_sb = lds_base;
+  auto stage_begin = [&](int slot) {
+    const bool past = cj >= k;
+    st_row0 = past ? last_row : row_c + cm * kTB * 32;
+    st_sb = lds_base + (unsigned)(slot * kSlotB);
+    if (cm == 0 && !past && wave < kMuI) {
+      // mu of the stage's cluster, with its first stage (reads past KP
+      // floats give 0 and stay inside the region)
+      const u32x4 rm = rsrc_words(mu + (size_t)cj * C::KP, C::KP * 4);
+      lds_load16(rm, st_sb + (unsigned)(kMuOff + 1024 * wave), voff0, 1024u * (unsigned)wave);
+    }
+  };
+  auto tile_load = [&](int tt, int mi) {
+    const int u0 = wave + 4 * mi;
+    const int u = u0 < kTileI ? u0 : kTileI - 1;  // wave-uniform
+    const int r0 = clamp_row(st_row0 + 32 * tt);
+    const u32x4 rb = rsrc_words((const unsigned char*)Ym + (size_t)r0 * (size_t)kLRow, 32 * kLRow);
+    // zeros past the tile's 32 rows
+    lds_load16(rb, st_sb + (unsigned)(tt * kTileCh * 16 + 1024 * u), voff0, 1024u * (unsigned)u);
+  };
+  auto issue = [&](int slot) {
+    stage_begin(slot);
+#pragma unroll
+    for (int tt = 0; tt < kTB; ++tt)
+#pragma unroll
+      for (int mi = 0; mi < kDw; ++mi) tile_load(tt, mi);
+  };
+  if constexpr (kLds) {
+    if (last_row >= 0) {  // block-uniform; an empty sample loads nothing
+      seek(0);
+      issue(0);
+      advance();
+      issue(1);
+      advance();
+    }
+  }
+
   for (int j = 0; j < k; ++j) {
     // ---- A operands for cluster j: x~ = x - mu_j (mu zero-padded to KP),
-    // rounded to the input precision, plus the augmentation
-    const float* m = mu + (size_t)j * C::KP + h * C::HALF;  // 16-byte aligned rows
+    // rounded to the input precision, plus the augmentation; m is this
+    // lane's half of mu_j (in memory, or in the LDS slot of the cluster's
+    // first stage)
+    auto buildA = [&](const float* m) {
     float mv[C::HALF];
 #pragma unroll
     for (int i0 = 0; i0 < C::HALF; i0 += V) {
@@ -514,7 +669,7 @@ __device__ __forceinline__ void p2_mfma_block(
       if constexpr (P == 2) {
 #pragma unroll
         for (int i = 0; i < C::HALF; ++i) {
-          const float v = xr[b][i] - mv[i];
+          const float v = xget(b, i) - mv[i];
           xq[i] = q_fp8(kFp8Scale * v);
           part = fmaf(v, v, part);  // the norm of the unrounded coordinates
         }
@@ -537,7 +692,7 @@ __device__ __forceinline__ void p2_mfma_block(
         bf16x2 pk[C::HALF / 2];
 #pragma unroll
         for (int i2 = 0; i2 < C::HALF / 2; ++i2) {
-          const f32x2 v = {xr[b][2 * i2] - mv[2 * i2], xr[b][2 * i2 + 1] - mv[2 * i2 + 1]};
+          const f32x2 v = {xget(b, 2 * i2) - mv[2 * i2], xget(b, 2 * i2 + 1) - mv[2 * i2 + 1]};
           pk[i2] = __builtin_convertvector(v, bf16x2);
           part = __builtin_amdgcn_fdot2_f32_bf16(pk[i2], pk[i2], part, false);
         }
@@ -557,7 +712,7 @@ __device__ __forceinline__ void p2_mfma_block(
       }
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) {
-        const float v = xr[b][i] - mv[i];
+        const float v = xget(b, i) - mv[i];
         xq[i] = v;
         part = fmaf(v, v, part);
       }
@@ -569,6 +724,8 @@ __device__ __forceinline__ void p2_mfma_block(
 #pragma unroll
       for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
     }
+    };
+    if constexpr (!kLds) buildA(mu + (size_t)j * C::KP + h * C::HALF);
 
     // ---- sweep the cluster's sample tiles (B operand double-buffered: the
     // next tile's loads are issued before this tile's MFMAs)
@@ -583,9 +740,14 @@ __device__ __forceinline__ void p2_mfma_block(
       for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
     }
     int g = 0;
-    // one tile: getB(q) gives step q of this lane's B fragment (a float2 of
-    // two steps for float32), from registers or read from LDS just in time
-    auto tile = [&](auto&& getB, float wj, int gj, int srow, bool last) {
+    // One tile, in four parts: chain (the MFMAs; getB(q) gives step q of
+    // this lane's B fragment, a float2 of two steps for float32, from
+    // registers or read from LDS just in time), fixup (pairs prone to
+    // cancellation, the cosine self pair), wsum_add (distances and the
+    // weighted sum) and fold (the float64 add every kFold tiles and at the
+    // cluster's end).  The LDS path overlaps the wsum_add of one tile with
+    // the chain of the next; the arithmetic per pair is the same.
+    auto chain = [&](auto&& getB, int gj, f32x16 (&cc)[PB]) {
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
         f32x16 c;
@@ -614,18 +776,27 @@ __device__ __forceinline__ void p2_mfma_block(
           for (int s = 0; s < C::NSTEP; ++s)
             c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], getB(s), c, 0, 0, 0, 0, 0, 0);
         }
+        cc[b] = c;
+      }
+    };
+    auto fixup = [&](f32x16 (&cc)[PB], int gj, int srow) {
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        f32x16& c = cc[b];
         if constexpr (P != 2 && M == kEucl) {
           // pairs prone to cancellation (kRecomputeThr) get their squared
-          // distance again from the float32 rows; rare outside the self pair
-          const float thr = __int_as_float(gj);
-          float mn = c[0];
+          // distance again from the float32 rows; rare outside the self pair.
+          // The threshold is >= 0, so comparing bit patterns as signed
+          // integers orders c like the values (every negative c, -0 included,
+          // compares below it): min3 on integers needs no NaN quieting.
+          int mn = __float_as_int(c[0]);
 #pragma unroll
-          for (int r = 1; r < 16; ++r) mn = fminf(mn, c[r]);
-          if (__builtin_expect(mn < thr, 0)) {
+          for (int r = 1; r < 16; ++r) mn = min(mn, __float_as_int(c[r]));
+          if (__builtin_expect(mn < gj, 0)) {
             // one code copy for the flagged rows, taken in turn
             unsigned flagged = 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) flagged |= (c[r] < thr ? 1u : 0u) << r;
+            for (int r = 0; r < 16; ++r) flagged |= (__float_as_int(c[r]) < gj ? 1u : 0u) << r;
             const float* yr = Y32 + (size_t)(srow + col) * DMY;
             while (flagged) {
               const int r = __builtin_ctz(flagged);
@@ -657,18 +828,25 @@ __device__ __forceinline__ void p2_mfma_block(
               if (r == rh) c[r] = 0.0f;
           }
         }
-        const float wt = P == 2 ? wj * (1.0f / S2) : wj;
+      }
+    };
+    auto wsum_add = [&](const f32x16 (&cc)[PB], float wj) {
+      const float wt = P == 2 ? wj * (1.0f / S2) : wj;
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           float dv;
           if (M == kEucl)
-            dv = __builtin_amdgcn_sqrtf(fabsf(c[r]));
+            dv = __builtin_amdgcn_sqrtf(fabsf(cc[b][r]));
           else
-            dv = __builtin_amdgcn_fmed3f(c[r], 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
+            dv = __builtin_amdgcn_fmed3f(cc[b][r], 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
           acc[b][r] = fmaf(wt, dv, acc[b][r]);
         }
       }
-      if (++g == kFold || last) {
+    };
+    auto fold = [&](bool last) {
+      if (__builtin_expect(++g == kFold || last, 0)) {
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
           wsum[b] += (double)transpose_reduce16(acc[b], lane);
@@ -678,79 +856,147 @@ __device__ __forceinline__ void p2_mfma_block(
         g = 0;
       }
     };
+    // The LDS path's chain with the pending tile's wsum_add woven in (one
+    // block of 32 elements per wave there): the B operand is read kAhead
+    // steps ahead of its MFMA, and each step carries a share of the pending
+    // tile's square roots and sums and of the loads of tile tt of the stage
+    // two ahead, issued while the MFMA runs.  Scheduling
+    // barriers keep the steps in this order (left to itself the compiler
+    // reads each step's operand right before its MFMA, which then waits for
+    // the whole LDS latency).  Same arithmetic per accumulator as
+    // chain + wsum_add.
+    auto chain_pipe = [&](auto&& getB, int gj, f32x16 (&cn)[PB], const f32x16 (&cp)[PB], float wp, int tt) {
+      static_assert(PB == 1, "the pipelined LDS path runs one block of 32 elements per wave");
+      constexpr int NS = C::NSTEP;
+      constexpr int kAhead = NS < 4 ? NS : 4;
+      const float wt = P == 2 ? wp * (1.0f / S2) : wp;
+      using BT = decltype(getB(0));
+      BT bq[kAhead];
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) bq[q] = getB(q);
+      f32x16 c;
+      if constexpr (P == 2) {
+        const float bcol = S2 * __int_as_float(gj);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[r] = nxc[0][r] + bcol;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[r] = 0.0f;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const BT cur = bq[q % kAhead];
+        if constexpr (P == 1)
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0].v[q], cur, c, 0, 0, 0);
+        else
+          c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[0].v[q], cur, c, 0, 0, 0, 0, 0, 0);
+        if (q + kAhead < NS) bq[q % kAhead] = getB(q + kAhead);
+        // the next-but-one stage's loads of tile tt, spread over the steps
+#pragma unroll
+        for (int mi = 0; mi < kDw; ++mi)
+          if (q == (2 * mi + 1) * NS / (2 * kDw)) tile_load(tt, mi);
+#pragma unroll
+        for (int r = 16 * q / NS; r < 16 * (q + 1) / NS; ++r) {
+          float dv;
+          if (M == kEucl)
+            dv = __builtin_amdgcn_sqrtf(fabsf(cp[0][r]));
+          else
+            dv = __builtin_amdgcn_fmed3f(cp[0][r], 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
+          acc[0][r] = fmaf(wt, dv, acc[0][r]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      cn[0] = c;
+    };
+    auto tile = [&](auto&& getB, float wj, int gj, int srow, bool last) {
+      f32x16 cc[PB];
+      chain(getB, gj, cc);
+      fixup(cc, gj, srow);
+      wsum_add(cc, wj);
+      fold(last);
+    };
     if constexpr (kLds) {
-      // Long rows: the block's four waves sweep the same tiles, so each tile
-      // is loaded once per block into LDS and every wave reads its B fragment
-      // from there.  Tiles go in stages of kTB (one barrier per stage),
-      // double-buffered: stage s + 1 is fetched into registers while stage s
-      // is computed, then stored to the other buffer.
-      auto fetch = [&](int row0) {
+      // pipelined: ca holds the tile whose sums are pending (zeros before
+      // the cluster's first); with two tiles per stage the two accumulator
+      // sets swap roles from tile to tile
+      f32x16 ca[PB], cb[PB];
+      float wa = 0.0f, wb = 0.0f;
+      if constexpr (kPipe) {
 #pragma unroll
-        for (int tt = 0; tt < kTB; ++tt) {
-          const int r0 = clamp_row(row0 + 32 * tt);
-          const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)r0 * (size_t)kRowB, 32 * kRowB);
+        for (int b = 0; b < PB; ++b)
 #pragma unroll
-          for (int i = 0; i < kPer; ++i) {
-            const int ci = threadIdx.x + 256 * i;
-            stage[tt][i] = ci < kNCh ? __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)ci, 0, 0) : u32x4{};
-          }
-          if (threadIdx.x < 32) {
-            sw[tt] = w[r0 + threadIdx.x];
-            sg[tt] = (M == kCos && P != 2) ? gid_pk[r0 + threadIdx.x] : __float_as_int(bnorm[r0 + threadIdx.x]);
-          }
-        }
-      };
-      auto store = [&](int buf) {
-#pragma unroll
-        for (int tt = 0; tt < kTB; ++tt) {
-#pragma unroll
-          for (int i = 0; i < kPer; ++i) {
-            const int ci = threadIdx.x + 256 * i;
-            if (ci < kNCh) {
-              const int r = ci / kChRow, q = ci - r * kChRow;
-              *(u32x4*)(ldsB + (buf * kTB + tt) * kTileB + r * kLRow + 16 * q) = stage[tt][i];
-            }
-          }
-          if (threadIdx.x < 32) {
-            ldsW[buf][32 * tt + threadIdx.x] = sw[tt];
-            ldsG[buf][32 * tt + threadIdx.x] = sg[tt];
-          }
-        }
-      };
-      if (ntile > 0 && pre != base) {  // block-uniform: every wave sweeps the same clusters
-        fetch(base);
-        store(cb);
-        pre = base;
-        __syncthreads();
+          for (int r = 0; r < 16; ++r) ca[b][r] = 0.0f;
       }
       for (int t = 0; t < ntile; t += kTB) {
-        const int buf = cb;
-        // the next stage: this cluster's next tiles, or after its last stage
-        // the next cluster's first tiles
-        const int nrow = clamp_row(t + kTB < ntile ? base + (t + kTB) * 32 : base + ntile * 32);
-        fetch(nrow);
-#pragma unroll
-        for (int tt = 0; tt < kTB; ++tt) {
-          if (t + tt < ntile) {  // block-uniform
-            const unsigned char* tl = ldsB + (buf * kTB + tt) * kTileB + col * kLRow + h * C::HALF * C::ELEM;
-            auto fromLds = [&](int q) {
-              if constexpr (P == 0) {
-                return *(const float2*)(tl + 8 * q);
-              } else if constexpr (P == 1) {
-                return *(const bf16x8*)(tl + 16 * q);
-              } else {
-                const u32x4 lo = *(const u32x4*)(tl + 32 * q), hi = *(const u32x4*)(tl + 32 * q + 16);
-                return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-              }
-            };
-            tile(fromLds, ldsW[buf][32 * tt + col], ldsG[buf][32 * tt + col], base + (t + tt) * 32,
-                 t + tt + 1 == ntile);
+        // this wave's loads of the stage are done once at most the next
+        // stage's remain in flight; the barrier makes every wave's visible
+        // and frees the slot the new loads go to (read two stages ago)
+        asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(kNIw) : "memory");
+        // the stage two ahead goes to the slot read two stages ago; its tile
+        // loads ride on this stage's MFMA steps (all at once off that path)
+        if constexpr (kPipe)
+          stage_begin(rs == 0 ? 2 : rs - 1);
+        else
+          issue(rs == 0 ? 2 : rs - 1);
+        advance();
+        const unsigned char* sb = ldsS + rs * kSlotB;
+        if (t == 0) buildA((const float*)(sb + kMuOff) + h * C::HALF);
+        auto fromLds = [&](int tt) {
+          const unsigned char* tl = sb + tt * kTileCh * 16 + col * kLRow + h * C::HALF * C::ELEM;
+          return [tl](int q) {
+            if constexpr (P == 0) {
+              return *(const float2*)(tl + 8 * q);
+            } else if constexpr (P == 1) {
+              return *(const bf16x8*)(tl + 16 * q);
+            } else {
+              const u32x4 lo = *(const u32x4*)(tl + 32 * q), hi = *(const u32x4*)(tl + 32 * q + 16);
+              return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+          };
+        };
+        auto wval = [&](int tt) { return *(const float*)(sb + tt * kTileCh * 16 + col * kLRow + kRowB); };
+        auto gval = [&](int tt) { return *(const int*)(sb + tt * kTileCh * 16 + col * kLRow + kRowB + 4); };
+        if constexpr (kPipe) {
+          // a tile's MFMAs and the pending tile's square roots and sums in one
+          // stretch of code, so the vector ALU works while the matrix core runs
+          {
+            const int g0 = gval(0);
+            chain_pipe(fromLds(0), g0, cb, ca, wa, 0);
+            if (t > 0) fold(false);
+            fixup(cb, g0, base + t * 32);
+            wb = wval(0);
           }
+          if (kTB == 2 && t + 1 < ntile) {  // block-uniform
+            const int g1 = gval(1);
+            chain_pipe(fromLds(1), g1, ca, cb, wb, 1);
+            fold(false);
+            fixup(ca, g1, base + (t + 1) * 32);
+            wa = wval(1);
+          } else {
+            // one tile in the stage: the pending tile is in cb (and the
+            // second tile of the stage two ahead is loaded here)
+            if constexpr (kTB == 2) {
+#pragma unroll
+              for (int mi = 0; mi < kDw; ++mi) tile_load(1, mi);
+            }
+#pragma unroll
+            for (int b = 0; b < PB; ++b) ca[b] = cb[b];
+            wa = wb;
+          }
+        } else {
+#pragma unroll
+          for (int tt = 0; tt < kTB; ++tt)
+            if (t + tt < ntile)  // block-uniform
+              tile(fromLds(tt), wval(tt), gval(tt), base + (t + tt) * 32, t + tt + 1 == ntile);
         }
-        store(buf ^ 1);
-        __syncthreads();
-        cb = buf ^ 1;
-        pre = nrow;
+        rs = rs == 2 ? 0 : rs + 1;
+      }
+      if constexpr (kPipe) {
+        if (ntile > 0) {
+          wsum_add(ca, wa);
+          fold(true);
+        }
       }
     } else {
       // Tiles go in pairs with unconditional prefetches, so the wait before
@@ -784,6 +1030,9 @@ __device__ __forceinline__ void p2_mfma_block(
       }
     }
   }
+  // the loads issued ahead of the last stages land in LDS before the block
+  // may end (its LDS can then go to another block)
+  if constexpr (kLds) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
   for (int b = 0; b < PB; ++b) {
     const int szo = csize[own[b]];
@@ -813,7 +1062,7 @@ __device__ __forceinline__ void p2_mfma_block(
 }
 
 template <int M, int P, int DM, int PB, int TBX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB, TBX>))) void k_p2_mfma(
     const float* __restrict__ X, int n, int d, const int32_t* __restrict__ labels,
     const void* __restrict__ Ym, const float* __restrict__ w, const int32_t* __restrict__ gid_pk,
     const int32_t* __restrict__ sp_off, const int32_t* __restrict__ cnt,
@@ -835,7 +1084,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
 // read through the constant address space, so their values sit in scalar
 // registers like kernel arguments.
 template <int M, int P, int DM, int PB, int TBX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB>))) void k_p2_mfma_jobs(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, P, DM, PB, TBX>))) void k_p2_mfma_jobs(
     const P2Job* __restrict__ jobs, const int2* __restrict__ items) {
   typedef const __attribute__((address_space(4))) P2Job* cjob_ptr;
   typedef const __attribute__((address_space(4))) int* citem_ptr;
@@ -856,9 +1105,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<M
 //     LDS path only).
 // The arithmetic of every element, and the 128-element partials of the
 // mean, are the same in every shape.
-bool mfma_lds_path(int prec, int DM) {
-  return prec == 2 ? round_up_c(DM, 64) / 2 > 40 : mfma_kp(prec, DM) / 2 > 30;
-}
 int mfma_pb_default(int prec, int DM) { return (prec == 0 && DM <= 32) ? 2 : 1; }
 int mfma_pb_max(int prec, int DM) { return (prec == 2 || DM > 64) ? 1 : 2; }
 int mfma_shapes(int prec, int DM, int* ids) {
@@ -912,11 +1158,11 @@ static void launch_jobs_one(hipStream_t st, const P2Job* jobs, const int2* items
 }
 
 template <int M, int P, int DM>
-static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, const int32_t* sp_off,
-                            const int32_t* cnt, int k, const float* mu, int S_pad, void* Ym,
-                            float* bnorm) {
+static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, const float* w,
+                            const int32_t* gid_pk, const int32_t* sp_off, const int32_t* cnt, int k,
+                            const float* mu, int S_pad, void* Ym, float* bnorm) {
   hipLaunchKernelGGL((k_pack_mfma<M, P, DM>), dim3((int)ceil_div(S_pad, 256)), dim3(256), 0, st, Y32,
-                     aux, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
+                     aux, w, gid_pk, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
 }
 
 #define SILH_MFMA_DISPATCH(FN, ...)                                     \
@@ -969,9 +1215,9 @@ static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, 
   } while (0)
 
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
-                      const int32_t* sp_off, const int32_t* cnt, int k, const float* mu, int S_pad,
-                      void* Ym, float* bnorm) {
-  SILH_MFMA_DISPATCH(launch_pack_one, st, Y32, aux, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
+                      const float* w, const int32_t* gid_pk, const int32_t* sp_off, const int32_t* cnt, int k,
+                      const float* mu, int S_pad, void* Ym, float* bnorm) {
+  SILH_MFMA_DISPATCH(launch_pack_one, st, Y32, aux, w, gid_pk, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
 }
 
 bool launch_phase2_mfma(hipStream_t st, int metric, int prec, int DM, const P2Args& A, const float* mu,

@@ -605,7 +605,7 @@ silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
     unsigned char* ym = nullptr;
     if (mfma_pack) {
       cv.add(&c->mu, (size_t)k * KP).add(&c->bnorm, (size_t)c->S_pad);
-      cv.add(&ym, (size_t)c->S_pad * KP * (prec == 0 ? 4 : (prec == 1 ? 2 : 1)));
+      cv.add(&ym, (size_t)c->S_pad * mfma_row_bytes(prec, c->DM));
     }
     CHK(cv.commit(c, c->alloc_sample));
     c->Ym = ym;
@@ -630,8 +630,8 @@ silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
     }
     {
       Launch L(c, K_PACK_MFMA);
-      if (!launch_pack_mfma(c->st, c->prm.metric, prec, c->DM, c->Y32, c->aux32, c->sp_off, c->cnt, k,
-                            c->mu, (int)c->S_pad, c->Ym, c->bnorm))
+      if (!launch_pack_mfma(c->st, c->prm.metric, prec, c->DM, c->Y32, c->aux32, c->w32, c->gid_pk, c->sp_off,
+                            c->cnt, k, c->mu, (int)c->S_pad, c->Ym, c->bnorm))
         return fail(SILH_E_UNSUPPORTED, "no MFMA packing for metric %d, d=%d", c->prm.metric, c->d);
       CHK(L.done());
     }

@@ -143,9 +143,8 @@ bool alloc_branch(silh_graph* g, Branch& b) {
             take(g, b.w32, S) && take(g, b.aux32, S) && take(g, b.Y32, S * DM) &&
             take(g, b.bpart, ceil_div(n, g->p2_rows));
   if (ok && g->mfma) {
-    const int64_t elem = g->mprec == 0 ? 4 : (g->mprec == 1 ? 2 : 1);
     unsigned char* ym = nullptr;
-    ok = take(g, b.mu, k * g->KP) && take(g, b.bnorm, S) && take(g, ym, S * g->KP * elem);
+    ok = take(g, b.mu, k * g->KP) && take(g, b.bnorm, S) && take(g, ym, S * (size_t)mfma_row_bytes(g->mprec, g->DM));
     b.Ym = ym;
   }
   if (ok && !g->mfma && phase2_valu_split(g->base.metric, g->DM)) ok = take(g, b.Wpart, n * k);
@@ -224,8 +223,8 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
   A.rn = g->rn;
   if (g->mfma) {
     launch_center(st, b.Y32, DM, g->KP, b.sp_off, b.cnt, k, b.mu);
-    if (!launch_pack_mfma(st, metric, g->mprec, DM, b.Y32, b.aux32, b.sp_off, b.cnt, k, b.mu, (int)g->S_cap, b.Ym,
-                          b.bnorm))
+    if (!launch_pack_mfma(st, metric, g->mprec, DM, b.Y32, b.aux32, b.w32, b.gid_pk, b.sp_off, b.cnt, k, b.mu,
+                          (int)g->S_cap, b.Ym, b.bnorm))
       return false;
     if (!launch_phase2_mfma(st, metric, g->mprec, DM, A, b.mu, b.Ym, b.bnorm, g->shape[(size_t)i]))
       return false;

@@ -97,8 +97,7 @@ void layout(const Shape& s, Slices& sl, Bufs& b) {
   sl.add(&b.p_gid, n).add(&b.gid_view, s.S_cap).add(&b.gid_pk, s.S_cap).add(&b.w32, s.S_cap);
   sl.add(&b.aux32, s.S_cap).add(&b.Y32, s.S_cap * s.DM).add(&b.bpart, ceil_div(n, s.p2_rows));
   if (s.mfma) {
-    const int64_t elem = s.mprec == 0 ? 4 : (s.mprec == 1 ? 2 : 1);
-    sl.add(&b.mu, k * s.KP).add(&b.bnorm, s.S_cap).add(&b.Ym, s.S_cap * s.KP * elem);
+    sl.add(&b.mu, k * s.KP).add(&b.bnorm, s.S_cap).add(&b.Ym, s.S_cap * (size_t)mfma_row_bytes(s.mprec, s.DM));
   }
   if (s.split) sl.add(&b.Wpart, n * k);
   if (s.cos) sl.add(&b.rn, n);
@@ -200,8 +199,8 @@ extern "C" silh_status silh_exact_noalloc(const silh_params* prm, const float* X
   bool ok = true;
   if (sh.mfma) {
     launch_center(st, B.Y32, DM, sh.KP, B.sp_off, B.cnt, k, B.mu);
-    ok = launch_pack_mfma(st, metric, sh.mprec, DM, B.Y32, B.aux32, B.sp_off, B.cnt, k, B.mu, (int)sh.S_cap, B.Ym,
-                          B.bnorm) &&
+    ok = launch_pack_mfma(st, metric, sh.mprec, DM, B.Y32, B.aux32, B.w32, B.gid_pk, B.sp_off, B.cnt, k, B.mu,
+                          (int)sh.S_cap, B.Ym, B.bnorm) &&
          launch_phase2_mfma(st, metric, sh.mprec, DM, A, B.mu, B.Ym, B.bnorm, pb_builtin(metric, sh.mprec, DM));
   } else {
     ok = launch_phase2_valu(st, metric, DM, A);

@@ -223,8 +223,8 @@ uint64_t estimate_bytes(const Dataset& ds, const silh_request& r) {
   if (S > n + 32ull * (uint64_t)r.k) S = n + 32ull * (uint64_t)r.k;
   const bool mfma = (r.metric == SILH_EUCL || r.metric == SILH_COS) && r.prec != SILH_FP32_VALU;
   const int mprec = r.prec == SILH_BF16 ? 1 : (r.prec == SILH_FP8 ? 2 : 0);
-  const uint64_t kp = mfma ? (uint64_t)silh::mfma_kp(mprec, DM) : 0;
-  const uint64_t row = (uint64_t)DM * 4 + kp * 4 + 24;
+  const uint64_t kp = mfma ? (uint64_t)silh::mfma_row_bytes(mprec, DM) : 0;
+  const uint64_t row = (uint64_t)DM * 4 + kp + 24;
   const uint64_t m = r.m > 0 ? (uint64_t)r.m : 0;  // row draws: ids, gathered rows, outputs
   // d > 128 Manhattan / Canberra: float64 partial sums per element and cluster
   const uint64_t split = (DM > 128 && (r.metric == SILH_MANH || r.metric == SILH_CANB)) ? n * (uint64_t)r.k * 8 : 0;
