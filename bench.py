@@ -277,23 +277,32 @@ def run_leg(native, Xd, Ld, k, metric, prec, t, seed, steps, a, b, s, work_fn=No
 def run_serving(native, torch, requests=48, load=0.5):
     """A short serving run: the resident 32-dataset pool, `requests` requests
     queued at once (saturation), then the same mix as Poisson arrivals at
-    load x saturation; p50/p99 latency overall and per metric."""
+    load x saturation; p50/p99 latency overall and per metric.  Both server
+    modes: Phase 2 of concurrent requests in shared launches ("batched") and
+    each request's own launch on its worker stream ("own"), at the same
+    arrival rate (load x the batched saturation)."""
     from paper_2607_01993_amd import serving
     specs, data, reqs = serving.build_workload(requests, torch.device("cuda:0"))
-    srv = native.Server(workers=4, hbm_budget_bytes=96 << 30, batched=True)
-    ids = [srv.add_dataset(X) for X in data]
-    serving.run_closed(srv, ids, reqs)  # warm-up: block caches, and the autotuner's keys of every request
-    res, secs = serving.run_closed(srv, ids, reqs)
-    sat = len(reqs) / secs
-    pairs = float(sum(specs[r["dataset"]]["n"] * x["S"] for r, x in zip(reqs, res)))
-    rr = serving.run_poisson(srv, ids, reqs, load * sat, seed=11)
-    summary = serving.summarize(rr, reqs)
-    launches = srv.launches()
-    srv.close()
-    return {"requests": len(reqs), "saturation_req_s": sat, "weighted_dist_evals_per_s_closed": pairs / secs,
-            "rate_req_s": load * sat, "latency_ms": summary, "shared_launches": launches,
-            "note": "32 resident datasets (n 1e4..2e6, d 16/64/256, eucl/cos bf16, manh/canb fp32), Voronoi "
-                    "requests k 2..128, t 64/256/1024; Phase 2 of concurrent requests in shared launches"}
+    out = {"requests": len(reqs),
+           "note": "32 resident datasets (n 1e4..2e6, d 16/64/256, eucl/cos bf16, manh/canb fp32), Voronoi "
+                   "requests k 2..128, t 64/256/1024"}
+    rate = None
+    for mode in ("batched", "own"):
+        srv = native.Server(workers=4, hbm_budget_bytes=96 << 30, batched=mode == "batched")
+        ids = [srv.add_dataset(X) for X in data]
+        serving.run_closed(srv, ids, reqs)  # warm-up: block caches, and the autotuner's keys of every request
+        res, secs = serving.run_closed(srv, ids, reqs)
+        sat = len(reqs) / secs
+        pairs = float(sum(specs[r["dataset"]]["n"] * x["S"] for r, x in zip(reqs, res)))
+        if rate is None:
+            rate = load * sat
+        rr = serving.run_poisson(srv, ids, reqs, rate, seed=11)
+        out[mode] = {"saturation_req_s": sat, "weighted_dist_evals_per_s_closed": pairs / secs, "rate_req_s": rate,
+                     "latency_ms": serving.summarize(rr, reqs), "shared_launches": srv.launches()}
+        srv.close()
+        print(f"# serving [{mode}]: saturation {sat:.1f} req/s, p50 {out[mode]['latency_ms']['p50_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def main():

@@ -130,6 +130,7 @@ constexpr int kSlots = 2;
 constexpr int kMaxTickJobs = 256;
 constexpr int kMaxTickItems = 1 << 16;
 struct Tick {
+  hipStream_t st = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   silh::P2Job* jobs_h = nullptr;  // pinned
   int2* items_h = nullptr;        // pinned
@@ -141,11 +142,11 @@ struct Tick {
   bool busy = false;
 };
 
-// The launches of one kernel class go to a stream of their own (so the
+// The launches of one kernel class go to streams of their own (so the
 // launches of a class with long blocks do not hold another class's), two in
-// flight at a time.
+// flight at a time, each slot on its own stream: the next launch of the class
+// starts on the CUs that the tail of the previous one leaves idle.
 struct Lane {
-  hipStream_t st = nullptr;
   Tick ticks[kSlots];
   int next = 0;              // slot of the next launch (the older one when both are busy)
   double ns_per_pair = 0.0;  // measured time per (element, sample) pair of the whole device, 0: none yet
@@ -160,17 +161,18 @@ void free_lane(Lane* L) {
     if (t.items_h) (void)hipHostFree(t.items_h);
     if (t.jobs_d) (void)hipFree(t.jobs_d);
     if (t.items_d) (void)hipFree(t.items_d);
+    if (t.st) (void)hipStreamDestroy(t.st);
   }
-  if (L->st) (void)hipStreamDestroy(L->st);
   delete L;
 }
 
 Lane* new_lane() {
   Lane* L = new (std::nothrow) Lane();
   if (!L) return nullptr;
-  bool ok = hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) == hipSuccess;
+  bool ok = true;
   for (Tick& t : L->ticks) {
-    ok = ok && hipEventCreate(&t.t0) == hipSuccess && hipEventCreate(&t.t1) == hipSuccess &&
+    ok = ok && hipStreamCreateWithFlags(&t.st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreate(&t.t0) == hipSuccess && hipEventCreate(&t.t1) == hipSuccess &&
          hipHostMalloc((void**)&t.jobs_h, sizeof(silh::P2Job) * kMaxTickJobs, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void**)&t.items_h, sizeof(int2) * kMaxTickItems, hipHostMallocDefault) == hipSuccess &&
          hipMalloc((void**)&t.jobs_d, sizeof(silh::P2Job) * kMaxTickJobs) == hipSuccess &&
@@ -543,7 +545,7 @@ void issue(silh_server* srv, Lane& L, Tick& t, int key, std::vector<Active*>& ac
   }
   if (ni == 0) return;
   t.blocks = ni;
-  const hipStream_t st = L.st;
+  const hipStream_t st = t.st;
   bool ok = hipMemcpyAsync(t.jobs_d, t.jobs_h, sizeof(silh::P2Job) * (size_t)nj, hipMemcpyHostToDevice, st) ==
                 hipSuccess &&
             hipMemcpyAsync(t.items_d, t.items_h, sizeof(int2) * (size_t)ni, hipMemcpyHostToDevice, st) == hipSuccess &&
