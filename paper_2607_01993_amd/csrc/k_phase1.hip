@@ -96,19 +96,71 @@ __device__ __forceinline__ double load_row(const float* __restrict__ X, int d, i
   return nx2;
 }
 
-// Rows too long for registers (d > 128): one wave per block keeps each lane's
-// row in LDS, column-major (xs[c * 64 + lane], conflict-free), 64 KB.
+// Rows too long for registers (d > 128): each thread streams its row from
+// memory in chunks of kWideC coordinates and evaluates the distances to a
+// group of kWideG rows of the initial sample together (kWideG independent
+// float64 chains, so the wave is not held by one chain's latency); the
+// group's rows sit in LDS, read by every lane at the same address.  Each
+// distance still takes its coordinates in increasing order.
 constexpr int kWideDM = 256;
-template <int M>
-__device__ __forceinline__ double load_row_col(const float* __restrict__ X, int d, int g, float* __restrict__ xs) {
-  const float* xr = X + (size_t)g * d;
+constexpr int kWideC = 32;
+constexpr int kWideG = 8;
+
+// coordinates [c0, c0 + kWideC) of row xr (zero from d on)
+__device__ __forceinline__ void load_chunk_wide(const float* __restrict__ xr, int d, int c0, bool vec,
+                                                float (&x)[kWideC]) {
+  if (vec) {
+#pragma unroll
+    for (int c = 0; c < kWideC; c += 4) {
+      const bool in = c0 + c < d;
+      const float4 v = *(const float4*)(xr + (in ? c0 + c : 0));
+      x[c] = in ? v.x : 0.0f;
+      x[c + 1] = in ? v.y : 0.0f;
+      x[c + 2] = in ? v.z : 0.0f;
+      x[c + 3] = in ? v.w : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kWideC; ++c) {
+      const bool in = c0 + c < d;
+      const float v = xr[in ? c0 + c : 0];
+      x[c] = in ? v : 0.0f;
+    }
+  }
+}
+
+// the squared norm of a streamed row, in coordinate order (cosine)
+__device__ __forceinline__ double row_norm2_wide(const float* __restrict__ xr, int d, bool vec) {
   double nx2 = 0.0;
-  for (int c = 0; c < kWideDM; ++c) {
-    const float v = c < d ? xr[c] : 0.0f;
-    xs[c * kWave] = v;
-    if (M == kCos) nx2 = nx2 + (double)v * (double)v;
+  for (int c0 = 0; c0 < kWideDM; c0 += kWideC) {
+    float x[kWideC];
+    load_chunk_wide(xr, d, c0, vec, x);
+#pragma unroll
+    for (int c = 0; c < kWideC; ++c) nx2 = nx2 + (double)x[c] * (double)x[c];
   }
   return nx2;
+}
+
+// distances from row xr to the kWideG rows ys[e][.] (stride kWideDM)
+template <int M>
+__device__ __forceinline__ void dist64_group_wide(const float* __restrict__ xr, int d, bool vec, double nx2,
+                                                  const double (*__restrict__ ys)[kWideDM],
+                                                  double (&dv)[kWideG]) {
+  double acc[kWideG], dot[kWideG], ny2[kWideG];
+#pragma unroll
+  for (int e = 0; e < kWideG; ++e) acc[e] = dot[e] = ny2[e] = 0.0;
+  for (int c0 = 0; c0 < kWideDM; c0 += kWideC) {
+    float x[kWideC];
+    load_chunk_wide(xr, d, c0, vec, x);
+#pragma unroll
+    for (int c = 0; c < kWideC; ++c) {
+      const double xc = (double)x[c];
+#pragma unroll
+      for (int e = 0; e < kWideG; ++e) dist64_step<M>(acc[e], dot[e], ny2[e], xc, ys[e][c0 + c]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kWideG; ++e) dv[e] = dist64_final<M>(acc[e], dot[e], ny2[e], nx2);
 }
 
 constexpr int kEB = 4;  // initial-sample rows summed together in the W pass
@@ -276,30 +328,48 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
   }
 }
 
-// d > 128: one wave per item of up to 64 members
+// d > 128: a 256-thread block per item (one member per thread), the item's
+// initial-sample rows staged kWideG at a time
 template <int M>
-__global__ __launch_bounds__(kWave) void k_w_partial_wide(const int32_t* __restrict__ items,
-                                                          const int32_t* __restrict__ perm,
-                                                          const float* __restrict__ X, int d,
-                                                          const double* __restrict__ f0X,
-                                                          double* __restrict__ partial) {
-  __shared__ float xs[kWideDM * kWave];
-  __shared__ double sh[1];
+__global__ __launch_bounds__(256) void k_w_partial_wide(const int32_t* __restrict__ items,
+                                                        const int32_t* __restrict__ perm,
+                                                        const float* __restrict__ X, int d,
+                                                        const double* __restrict__ f0X,
+                                                        double* __restrict__ partial, DistStore ds) {
+  __shared__ double ys[kWideG][kWideDM];
+  __shared__ double sh[4];
   const int32_t* it = items + (size_t)blockIdx.x * 6;
   const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
+  double* keep = nullptr;
+  int64_t kstride = 0;
+  if (ds.d != nullptr && f0n > 0 && *ds.use) {
+    const int j = it[0];
+    kstride = ds.off[j + 1] - ds.off[j];
+    keep = ds.d + ds.base[j] + (begin - ds.off[j]) + threadIdx.x;
+  }
   const int r = begin + threadIdx.x;
   const bool have = r < end;
-  float* xl = xs + threadIdx.x;
-  double nx2 = 0.0;
-  if (have) {
-    nx2 = load_row_col<M>(X, d, perm[r], xl);
-  } else {
-    for (int c = 0; c < kWideDM; ++c) xl[c * kWave] = 0.0f;
-  }
-  for (int e = 0; e < f0n; ++e) {
-    const double dv = dist64_col<M, kWideDM>(xl, nx2, f0X + (size_t)(f0b + e) * kWideDM);
-    const double tot = block_sum_f64<kWave>(have ? dv : 0.0, sh);
-    if (threadIdx.x == 0) partial[pb + e] = tot;
+  const float* xr = X + (size_t)(have ? perm[r] : 0) * d;
+  const bool vec = (d & 3) == 0 && ((uintptr_t)X & 15) == 0;
+  const double nx2 = M == kCos ? row_norm2_wide(xr, d, vec) : 0.0;
+  for (int e0 = 0; e0 < f0n; e0 += kWideG) {
+    const int ne = f0n - e0 < kWideG ? f0n - e0 : kWideG;  // uniform over the block
+    __syncthreads();
+    for (int q = threadIdx.x; q < kWideG * kWideDM; q += 256) {
+      const int e = q / kWideDM, c = q - e * kWideDM;
+      ys[e][c] = f0X[(size_t)(f0b + e0 + (e < ne ? e : ne - 1)) * kWideDM + c];  // past ne: a copy
+    }
+    __syncthreads();
+    double dv[kWideG];
+    dist64_group_wide<M>(xr, d, vec, nx2, ys, dv);
+#pragma unroll
+    for (int e = 0; e < kWideG; ++e) {
+      if (e < ne) {
+        if (keep != nullptr && have) keep[(int64_t)(e0 + e) * kstride] = dv[e];
+        const double tot = block_sum_f64<256>(have ? dv[e] : 0.0, sh);
+        if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
+      }
+    }
   }
 }
 
@@ -334,7 +404,7 @@ void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, 
                       DistStore ds) {
   if (nitems <= 0) return;
   if (DM == kWideDM) {
-#define SILH_WP(MM) hipLaunchKernelGGL(k_w_partial_wide<MM>, dim3(nitems), dim3(kWave), 0, st, items, perm, X, d, f0X, partial)
+#define SILH_WP(MM) hipLaunchKernelGGL(k_w_partial_wide<MM>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial, ds)
     switch (metric) {
       case kEucl: SILH_WP(kEucl); break;
       case kCos: SILH_WP(kCos); break;
@@ -468,18 +538,20 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
   flag[i] = sel;
 }
 
-// d > 128: one wave per block, the element's row in LDS
+// d > 128: the kept distances where the W pass kept them (as k_draw), else
+// the element's row streamed against its cluster's initial sample, kWideG
+// rows at a time straight from memory
 template <int M>
-__global__ __launch_bounds__(kWave) void k_draw_wide(int sampler, const int32_t* __restrict__ perm,
-                                                     const int32_t* __restrict__ slab, int n,
-                                                     const float* __restrict__ X, int d,
-                                                     const int32_t* __restrict__ csize, int64_t t,
-                                                     uint64_t seed, const int32_t* __restrict__ f0_off,
-                                                     const double* __restrict__ f0X,
-                                                     const double* __restrict__ W,
-                                                     double* __restrict__ p_gid, int32_t* __restrict__ flag) {
-  __shared__ float xs[kWideDM * kWave];
-  const int i = blockIdx.x * kWave + threadIdx.x;
+__global__ __launch_bounds__(256) void k_draw_wide(int sampler, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ slab, int n,
+                                                   const float* __restrict__ X, int d,
+                                                   const int32_t* __restrict__ csize, int64_t t,
+                                                   uint64_t seed, const int32_t* __restrict__ f0_off,
+                                                   const double* __restrict__ f0X,
+                                                   const double* __restrict__ W,
+                                                   double* __restrict__ p_gid, int32_t* __restrict__ flag,
+                                                   DistStore ds) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int g = perm[i];
   const int j = slab[i];
@@ -495,15 +567,45 @@ __global__ __launch_bounds__(kWave) void k_draw_wide(int sampler, const int32_t*
     sel = uniform53(seed, (uint64_t)g, kStreamUNI) < p ? 1 : 0;
   } else {
     double gam = 1.0 / (double)m;
-    float* xl = xs + threadIdx.x;
-    const double nx2 = load_row_col<M>(X, d, g, xl);
-    const int fb = f0_off[j], fe = f0_off[j + 1];
-    for (int e = fb; e < fe; ++e) {
-      const double w = W[e];
-      const double dv = dist64_col<M, kWideDM>(xl, nx2, f0X + (size_t)e * kWideDM);
-      if (w > 0.0) {
-        const double r = dv / w;
-        gam = r > gam ? r : gam;
+    const int fb = f0_off[j], fn = f0_off[j + 1] - fb;
+    if (ds.d != nullptr && *ds.use && i >= ds.off[j] && i < ds.off[j + 1]) {
+      const int64_t stride = ds.off[j + 1] - ds.off[j];
+      const double* kd = ds.d + ds.base[j] + (i - ds.off[j]);
+      for (int e0 = 0; e0 < fn; e0 += kDrawB) {
+        double wv[kDrawB], dv[kDrawB];
+#pragma unroll
+        for (int e = 0; e < kDrawB; ++e) {
+          const int ee = e0 + e < fn ? e0 + e : fn - 1;
+          wv[e] = W[fb + ee];
+          dv[e] = kd[(int64_t)ee * stride];
+        }
+#pragma unroll
+        for (int e = 0; e < kDrawB; ++e) {
+          if (wv[e] > 0.0) {
+            const double r = dv[e] / wv[e];
+            gam = r > gam ? r : gam;
+          }
+        }
+      }
+    } else {
+      const float* xr = X + (size_t)g * d;
+      const bool vec = (d & 3) == 0 && ((uintptr_t)X & 15) == 0;
+      const double nx2 = M == kCos ? row_norm2_wide(xr, d, vec) : 0.0;
+      for (int e = 0; e < fn; ++e) {
+        const double* y = f0X + (size_t)(fb + e) * kWideDM;
+        double acc = 0.0, dot = 0.0, ny2 = 0.0;
+        for (int c0 = 0; c0 < kWideDM; c0 += kWideC) {
+          float x[kWideC];
+          load_chunk_wide(xr, d, c0, vec, x);
+#pragma unroll
+          for (int c = 0; c < kWideC; ++c) dist64_step<M>(acc, dot, ny2, (double)x[c], y[c0 + c]);
+        }
+        const double dv = dist64_final<M>(acc, dot, ny2, nx2);
+        const double w = W[fb + e];
+        if (w > 0.0) {
+          const double r = dv / w;
+          gam = r > gam ? r : gam;
+        }
       }
     }
     p = (double)t * gam;
@@ -519,7 +621,7 @@ void launch_draw(hipStream_t st, int metric, int DM, int sampler, const int32_t*
                  uint64_t seed, const int32_t* f0_off, const double* f0X, const double* W,
                  double* p_gid, int32_t* flag, DistStore ds) {
   if (DM == kWideDM) {
-#define SILH_DW(MM) hipLaunchKernelGGL(k_draw_wide<MM>, dim3((int)ceil_div(n, kWave)), dim3(kWave), 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag)
+#define SILH_DW(MM) hipLaunchKernelGGL(k_draw_wide<MM>, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, sampler, perm, slab, n, X, d, csize, t, seed, f0_off, f0X, W, p_gid, flag, ds)
     switch (metric) {
       case kEucl: SILH_DW(kEucl); break;
       case kCos: SILH_DW(kCos); break;

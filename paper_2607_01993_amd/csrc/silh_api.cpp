@@ -697,9 +697,8 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
     const int64_t f0_cap = std::min<int64_t>(n, 64 * (int64_t)k + 1024);
     const int64_t items_cap = ceil_div(n, chunk) + k;
     const int64_t part_cap = std::min<int64_t>((int64_t)1 << 30, items_cap * 64);
-    // the W pass keeps its distances for the draw when they fit (rows of
-    // d > 128 are evaluated again: their kernels keep nothing)
-    const int64_t dist_cap = c->DM > 128 ? 0 : dist_capacity(n, std::log(5.0 * (double)k / c->prm.delta));
+    // the W pass keeps its distances for the draw when they fit
+    const int64_t dist_cap = dist_capacity(n, std::log(5.0 * (double)k / c->prm.delta));
     {
       Carve cv;
       cv.add(&c->f0_gid, (size_t)f0_cap).add(&c->f0_cl, (size_t)f0_cap).add(&c->f0X, (size_t)f0_cap * c->DM);

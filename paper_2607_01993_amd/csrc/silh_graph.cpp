@@ -299,8 +299,8 @@ silh_status silh_graph_create(const silh_params* base, const float* X, const int
   g->F0_cap = std::min<int64_t>(g->n, 64 * (int64_t)g->kmax + 1024);
   g->items_cap = ceil_div(g->n, g->chunk) + g->kmax;
   g->part_cap = std::min<int64_t>((int64_t)1 << 30, g->items_cap * 64);
-  // member distances kept by the W pass for the draw (d <= 128; the largest k)
-  g->dist_cap = (base->sampler == SILH_PPS && g->DM <= 128)
+  // member distances kept by the W pass for the draw (the largest k)
+  g->dist_cap = base->sampler == SILH_PPS
                     ? dist_capacity(g->n, std::log(5.0 * (double)g->kmax / base->delta))
                     : 0;
   g->br.resize((size_t)chains);

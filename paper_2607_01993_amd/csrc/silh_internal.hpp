@@ -15,7 +15,7 @@ inline int sort_seg(int64_t n, int k) {
 constexpr int kScanTile = 2048;
 // Members per work item of the W(e_bar) partial sums.
 constexpr int kWChunk = 256;   // one member per thread of a 256-thread block
-constexpr int kWChunkWide = 64;  // d > 128: one member per lane of a one-wave block
+constexpr int kWChunkWide = 256;  // d > 128: one member per thread as well
 // Sample rows of each cluster are padded to a multiple of this.
 constexpr int kSamplePad = 32;
 // Rows per Phase-2 block in the VALU kernel.

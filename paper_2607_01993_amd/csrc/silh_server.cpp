@@ -230,9 +230,9 @@ uint64_t estimate_bytes(const Dataset& ds, const silh_request& r) {
   const uint64_t m = r.m > 0 ? (uint64_t)r.m : 0;  // row draws: ids, gathered rows, outputs
   // d > 128 Manhattan / Canberra: float64 partial sums per element and cluster
   const uint64_t split = (DM > 128 && (r.metric == SILH_MANH || r.metric == SILH_CANB)) ? n * (uint64_t)r.k * 8 : 0;
-  // PPS with d <= 128: the W pass keeps its distances for the draw (allocated
-  // at their capacity)
-  const uint64_t kept = (r.sampler == SILH_PPS && DM <= 128)
+  // PPS: the W pass keeps its distances for the draw (allocated at their
+  // capacity)
+  const uint64_t kept = r.sampler == SILH_PPS
                             ? 8 * (uint64_t)silh::dist_capacity((int64_t)n, std::log(5.0 * r.k / r.delta))
                             : 0;
   // cosine: one float32 reciprocal norm per element
