@@ -36,6 +36,11 @@ SOURCES = {
     "k_phase2_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
+# sources with instructions in inline asm whose wait states the compiler does
+# not manage: their device assembly is kept from the compile and checked
+# (asm_check.py); a hazard fails the build
+CHECK_ASM = {"k_phase2_mfma.hip"}
+
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
@@ -53,15 +58,36 @@ def hipcc() -> str:
 
 
 def _compile(src: str, extra) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    stem = os.path.splitext(src)[0]
+    obj = os.path.join(BUILD, stem + ".o")
     # SILH_EXTRA_HIPFLAGS: extra compiler flags (tuning experiments)
     more = os.environ.get("SILH_EXTRA_HIPFLAGS", "").split()
-    cmd = [hipcc(), *COMMON, *extra, *more, "-c", os.path.join(CSRC, src), "-o", obj]
+    temps = os.path.join(BUILD, "temps_" + stem) if src in CHECK_ASM else None
+    out = obj
+    if temps:
+        shutil.rmtree(temps, ignore_errors=True)
+        os.makedirs(temps)
+        out = os.path.join(temps, stem + ".o")
+        more = more + ["-save-temps=obj"]
+    cmd = [hipcc(), *COMMON, *extra, *more, "-c", os.path.join(CSRC, src), "-o", out]
     if src.endswith(".hip"):
         cmd.insert(1, "-xhip")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if temps:
+        try:
+            from . import asm_check
+        except ImportError:  # run as a script from this directory
+            import asm_check
+        dev = [f for f in os.listdir(temps) if f.endswith(f"-{ARCH}.s")]
+        if len(dev) != 1:
+            raise RuntimeError(f"{src}: device assembly not found in {temps}")
+        found = asm_check.check(os.path.join(temps, dev[0]))
+        if found:
+            raise RuntimeError(f"{src}: wait-state hazards in the device code:\n" + "\n".join(found[:20]))
+        os.replace(out, obj)
+        shutil.rmtree(temps, ignore_errors=True)
     warn = "\n".join(ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln
                      and "unknown target feature" not in ln and ln.strip())
     if warn.strip():

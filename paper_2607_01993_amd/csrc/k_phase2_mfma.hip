@@ -18,16 +18,21 @@
 //   cosine:     d = med3(c, 0, 2) with c = |x~ - y~|^2 / 2 + u_x + u_y
 //               (u = 0.5 for a zero vector, else 0, which makes d = 1 there).
 //
-// Tile mapping (v_mfma_f32_32x32x{2f32,16_bf16}): a wave owns 32 elements (the
-// A operand rows); each 32-column tile is 32 samples of one cluster (the B
-// operand columns, cluster blocks padded to 32 with zero-weight rows).  Lane l
-// holds sample column l%32 of the accumulator and 16 element rows, so its
-// weight is a single register; per-row partial sums stay in registers across
-// the cluster's tiles and are combined across the 32 columns by a
-// transpose-reduction (5 exchange steps) when the cluster ends or every kFold
-// tiles, then added in float64.  The contraction order is free, so each lane
-// feeds the MFMA a contiguous half of the (augmented) row: half h = l/32 of
-// the row holds logical coordinates [h*HALF, (h+1)*HALF).
+// Tile mapping (v_mfma_f32_32x32x{2f32,16_bf16}, 32x32x64 f8f6f4): a wave
+// owns 32 elements (the B operand columns); each tile is 32 samples of one
+// cluster (the A operand rows, cluster blocks padded to 32 with zero-weight
+// rows).  Lane l holds element column l%32 of the accumulator and the 16
+// sample rows 8g + 4h + r (h = l/32, g, r < 4), so all 16 terms of a tile go
+// into the lane's own element: four running float32 sums per lane, each
+// term's weight taken from a neighbouring lane by a DPP broadcast inside the
+// FMA, and one exchange between the two halves when the cluster ends or
+// every kFold tiles, then added in float64.  The pipelined LDS path (long
+// rows, bf16 / fp8) keeps the other orientation, elements as the rows (see
+// kT in p2_mfma_block).  The contraction order is free,
+// so each lane feeds the MFMA a contiguous half of the (augmented) row: half
+// h of the row holds logical coordinates [h*HALF, (h+1)*HALF).
+#include <utility>
+
 #include "device_common.hpp"
 #include "silh_internal.hpp"
 
@@ -53,22 +58,37 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // 0.3 % of W_hat at d = 128, against under 0.02 % this way).
 constexpr float kFp8Scale = 64.0f;
 
-constexpr int kFold = 32;  // tiles summed in float32 before the float64 add
+// tiles summed in float32 before the float64 add: with samples as the rows
+// each of a lane's four sums takes four terms per tile; with elements as the
+// rows each of its 16 sums takes one
+template <int P, bool T>
+constexpr int kFold = T ? (P == 0 ? 8 : 16) : 32;
 
 // Pairs prone to cancellation in the expanded form: with x~, y~ centred on
 // mu_j, the squared distance c = |x~|^2 + |y~|^2 - 2 x~.y~ carries
 // an absolute error of order eps (|x~|^2 + |y~|^2), so a pair with
 // c < tau (|x~|^2 + |y~|^2) loses more than eps/tau of its relative accuracy
-// (and the square root halves that).  Such a pair has |x~| < 2|y~| when
-// tau < 0.2 (else c >= (|x~| - |y~|)^2 >= |x~|^2/4), hence c < 5 tau |y~|^2:
-// every pair with c below 6 tau |y~|^2 (a margin for the error of c itself)
-// is evaluated again as sum (x - y)^2 from the float32 rows, which has no
-// cancellation.  tau = 2^-5 for float32 operands (relative error of d below
+// (and the square root halves that).  Such a pair has |y~| < 2|x~| when
+// tau < 0.2 (else c >= (|y~| - |x~|)^2 >= |y~|^2/4), hence c < 5 tau |x~|^2:
+// every pair with c below 6 tau |x~|^2 (a margin for the error of c itself),
+// a threshold of the element alone, is evaluated again as sum (x - y)^2 from
+// the float32 rows, which has no cancellation.  tau = 2^-5 for float32 operands (relative error of d below
 // 2^-17 for the others) and 2^-8 for bf16 (whose own rounding of x~ and y~
 // dominates below that).  The self pair d(e, e) is one of them and comes out
 // exactly 0.
 template <int P>
 constexpr float kRecomputeThr = P == 0 ? 6.0f / 32.0f : 6.0f / 256.0f;
+
+// The test can only flag a pair whose element is near the cluster's sample:
+// with R^2 the largest |y~_q|^2 of the sample and |x~_q|^2 >= f R^2, every
+// pair has |x~_q - y~_q| >= (1 - 1/sqrt f) |x~_q|, so c >= (1 - 1/sqrt f)^2
+// |x~_q|^2 less a float32 rounding error far below that: above the threshold
+// 6 tau |x~_q|^2 for f = 2.25 with bf16 (0.111 against 0.023 times
+// |x~_q|^2) and f = 4 with float32 (0.25 against 0.19).  A block whose 32
+// elements all lie that far out skips the test for the cluster (the same
+// results, no test instructions in its tiles).
+template <int P>
+constexpr float kSkipFactor = P == 0 ? 4.0f : 2.25f;
 
 constexpr int kCenterRows = 256;
 
@@ -101,6 +121,8 @@ bool mfma_lds_path(int prec, int DM) {
   return prec == 2 ? round_up_c(DM, 64) / 2 > 40 : mfma_kp(prec, DM) / 2 > 30;
 }
 
+size_t mfma_mu_floats(int prec, int DM, int k) { return (size_t)k * mfma_kp(prec, DM) + k; }
+
 int mfma_row_bytes(int prec, int DM) {
   return mfma_kp(prec, DM) * (prec == 0 ? 4 : (prec == 1 ? 2 : 1)) + (mfma_lds_path(prec, DM) ? 16 : 0);
 }
@@ -126,7 +148,7 @@ __device__ __forceinline__ void split3(float v, float& h, float& m, float& l) {
 // ----------------------------------------------------------------------------
 // centre of each cluster's sample: mean of its first kCenterRows rows of Y32
 // (float64 sums; any point of the cluster would do, the mean keeps the
-// centred operands smallest)
+// centred operands smallest); one block per cluster (grid = k)
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_center(const float* __restrict__ Y32, int DM, int KP,
                                                 const int32_t* __restrict__ sp_off,
@@ -134,6 +156,8 @@ __global__ __launch_bounds__(256) void k_center(const float* __restrict__ Y32, i
                                                 float* __restrict__ mu) {
   __shared__ double part[256];
   const int j = blockIdx.x;
+  // the cluster's squared radius, the packing takes its maximum
+  if (threadIdx.x == 0) mu[(size_t)gridDim.x * KP + j] = 0.0f;
   const int m = cnt[j] < kCenterRows ? cnt[j] : kCenterRows;
   const int base = sp_off[j];
   // coordinate chunks of up to 32 columns; 8 row groups per chunk
@@ -162,12 +186,16 @@ void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32
 }
 
 // ----------------------------------------------------------------------------
-// B operand rows: [ -2 alpha y~_q (DM) | augmentation | 0 ... ] with
+// Sample operand rows: [ -2 alpha y~_q (DM) | augmentation | 0 ... ] with
 // alpha = 1 (Euclidean) or 1/2 (cosine); y~_q = y~ rounded to the input
-// precision; the augmentation carries alpha |y~_q|^2 + u_y.  Padding rows are
-// all zero.  On the LDS path each row ends in 16 bytes: the weight w, the
-// per-sample value (Euclidean: the recompute threshold; fp8: the norm term;
-// cosine: the element id), two zero words.
+// precision; the augmentation carries alpha |y~_q|^2 + u_y and the ones that
+// take in the element's norm term.  Padding rows keep only those ones, so an
+// element meets them at c = its own norm term (never below its recompute
+// threshold) with weight 0.  bnorm and, on the LDS path, each row's 16-byte
+// tail carry the per-sample value (fp8: the norm term; cosine: the element
+// id; Euclidean: the sample's recompute threshold, which the element-row
+// layout tests against); the tail also holds the weight w and two zero
+// words.
 // ----------------------------------------------------------------------------
 template <int M, int P, int DM>
 __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32,
@@ -176,7 +204,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
                                                    const int32_t* __restrict__ gid_pk,
                                                    const int32_t* __restrict__ sp_off,
                                                    const int32_t* __restrict__ cnt, int k,
-                                                   const float* __restrict__ mu, int S_pad,
+                                                   float* __restrict__ mu, int S_pad,
                                                    void* __restrict__ Ym, float* __restrict__ bnorm) {
   using C = MCfg<P, DM>;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,6 +245,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
       *(u32x4*)(out + C::KP / 4) = u32x4{__float_as_uint(w[s]), __float_as_uint(bn), 0u, 0u};
     return;
   }
+  // Euclidean, element-row layout: the sample's recompute threshold
   float thr = 0.0f;
   if (real) {
     const float* y = Y32 + (size_t)s * DM;
@@ -231,13 +260,19 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
     }
     const float bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
     thr = M == kEucl ? kRecomputeThr<P> * ny : 0.0f;
+    // the cluster's squared radius: the largest ny (>= 0, so its bits order
+    // like the values)
+    if (M == kEucl) atomicMax((int*)(mu + (size_t)k * C::KP + j), __float_as_int(ny));
     if (P == 0) {
-      row[DM] = 1.0f;
       row[DM + 1] = bn;
     } else {
-      row[DM] = row[DM + 1] = row[DM + 2] = 1.0f;
       split3(bn, row[DM + 3], row[DM + 4], row[DM + 5]);
     }
+  }
+  if (P == 0) {
+    row[DM] = 1.0f;
+  } else {
+    row[DM] = row[DM + 1] = row[DM + 2] = 1.0f;
   }
   bnorm[s] = thr;
   unsigned char* rowp = (unsigned char*)Ym + (size_t)s * C::ROWB;
@@ -257,7 +292,65 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
 }
 
 // ----------------------------------------------------------------------------
-// 16 per-lane row sums, each over the lane's column: five exchange steps, each
+// The weighted sums of a tile: accumulator row r of lane l is sample row
+// 8 (r >> 2) + 4 h + (r & 3) of the tile (h = l >> 5).  A lane holds two
+// weights, wv[0] = w[(l & 11) + 4h] and wv[1] = w[16 + (l & 11) + 4h], so
+// within each 16-lane row, lane (r & 3) + 8 ((r >> 2) & 1) of wv[r >> 3]
+// holds the weight of row r for every lane of that 16-lane row: a DPP
+// broadcast (row_newbcast) inside the FMA reads it.  The compiler does not
+// fuse a DPP move into v_fmac_f32, so the FMAs are written as asm; a DPP
+// source written by the vector ALU needs two wait states, a square root's
+// result one before a non-transcendental use.
+// ----------------------------------------------------------------------------
+__host__ __device__ constexpr int wsrc_lane(int r) { return (r & 3) + 8 * ((r >> 2) & 1); }
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1 (indices the DPP
+// controls and asm operands need as constants)
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// lane l's index into its tile's weights (and other per-row values): the
+// two loads take rows wrow(l) and 16 + wrow(l)
+__device__ __forceinline__ int wrow(int lane) { return (lane & 11) + 4 * (lane >> 5); }
+
+// acc[r & 3] += w(row r) * dv[r] for the 16 rows, after two wait states
+__device__ __forceinline__ void wsum16(float (&acc)[4], float w0, float w1, const float (&dv)[16]) {
+#define SILH_FMAC(A, W, V, Q) "v_fmac_f32_dpp %" #A ", %" #W ", %" #V " row_newbcast:" #Q " row_mask:0xf bank_mask:0xf\n\t"
+  asm("s_nop 1\n\t"
+      SILH_FMAC(0, 4, 6, 0) SILH_FMAC(1, 4, 7, 1) SILH_FMAC(2, 4, 8, 2) SILH_FMAC(3, 4, 9, 3)
+      SILH_FMAC(0, 4, 10, 8) SILH_FMAC(1, 4, 11, 9) SILH_FMAC(2, 4, 12, 10) SILH_FMAC(3, 4, 13, 11)
+      SILH_FMAC(0, 5, 14, 0) SILH_FMAC(1, 5, 15, 1) SILH_FMAC(2, 5, 16, 2) SILH_FMAC(3, 5, 17, 3)
+      SILH_FMAC(0, 5, 18, 8) SILH_FMAC(1, 5, 19, 9) SILH_FMAC(2, 5, 20, 10) SILH_FMAC(3, 5, 21, 11)
+      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])
+      : "v"(w0), "v"(w1), "v"(dv[0]), "v"(dv[1]), "v"(dv[2]), "v"(dv[3]), "v"(dv[4]), "v"(dv[5]), "v"(dv[6]),
+        "v"(dv[7]), "v"(dv[8]), "v"(dv[9]), "v"(dv[10]), "v"(dv[11]), "v"(dv[12]), "v"(dv[13]), "v"(dv[14]),
+        "v"(dv[15]));
+#undef SILH_FMAC
+}
+
+// per-row value v of row r (the same broadcast, for the compiler's own
+// DPP-combined adds)
+template <int R>
+__device__ __forceinline__ float row_val(float v0, float v1) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(R < 8 ? v0 : v1), 0x150 + wsrc_lane(R), 0xF, 0xF, true));
+}
+
+// the sum of a lane's four running sums and its partner's in the other half
+// (lanes l and l ^ 32 hold the same element)
+__device__ __forceinline__ float lane_sum(const float (&acc)[4]) {
+  const float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// ----------------------------------------------------------------------------
+// Element-row layout: 16 per-lane row sums, each over the lane's column: five exchange steps, each
 // pairing lanes that differ in one bit of the column index and halving the
 // number of live values (the partner receives the half it keeps).  Partners:
 // lane ^ 16 by a row swap between two registers, then within 16-lane rows by
@@ -404,14 +497,15 @@ __device__ __forceinline__ void load_chunk(const float* __restrict__ xp, int c, 
   }
 }
 
-// one tile's B operand (this lane's half row), weight and the sample's
-// per-row value: fp8 its norm term, Euclidean its recompute threshold (both
-// in bnorm), cosine its element id (gid_pk)
+// one tile's sample operand (this lane's half row), the weights of rows
+// wrow(lane) and 16 + wrow(lane), and per-row values: fp8 the norm terms of
+// those two rows (bnorm), cosine the element id of row lane % 32 (gid_pk)
 template <int M, int P, int DM>
 __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const float* __restrict__ w,
                                           const int32_t* __restrict__ gid_pk,
                                           const float* __restrict__ bnorm, int row0, uint32_t lane_off,
-                                          uint32_t col, BFrag<P, DM>& b, float& wj, int& gj) {
+                                          uint32_t col, uint32_t wr, BFrag<P, DM>& b, float (&wv)[2],
+                                          int (&gv)[2]) {
   using C = MCfg<P, DM>;
   // row0 is wave-uniform: each 32-row tile gets buffer descriptors built on
   // the scalar unit, and a lane reads at a fixed byte offset (no per-tile
@@ -419,7 +513,7 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
   const auto rb = rsrc_at((const unsigned char*)Ym + (size_t)row0 * (size_t)(C::KP * C::ELEM),
                           32 * C::KP * C::ELEM);
   const auto rw = rsrc_at(w + row0, 32 * 4);
-  const auto rg = rsrc_at((M == kCos && P != 2) ? (const void*)(gid_pk + row0) : (const void*)(bnorm + row0), 32 * 4);
+  const auto rg = rsrc_at(P != 2 ? (const void*)(gid_pk + row0) : (const void*)(bnorm + row0), 32 * 4);
   if constexpr (P == 2) {
 #pragma unroll
     for (int s = 0; s < C::NSTEP; ++s) {
@@ -436,8 +530,14 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
     for (int s = 0; s < C::NSTEP; ++s)
       b.v[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 16u * s, 0, 0));
   }
-  wj = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * col, 0, 0));
-  gj = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0);
+  wv[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * wr, 0, 0));
+  wv[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * (wr + 16u), 0, 0));
+  if constexpr (P == 2) {
+    gv[0] = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * wr, 0, 0);
+    gv[1] = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * (wr + 16u), 0, 0);
+  } else if constexpr (M == kCos) {
+    gv[0] = (int)__builtin_amdgcn_raw_buffer_load_b32(rg, 4u * col, 0, 0);
+  }
 }
 
 // waves per SIMD the one-block shapes from d = 32 on keep (their occupancy
@@ -473,7 +573,7 @@ __device__ __forceinline__ void p2_mfma_block(
   __shared__ double sh32[4 * PB];  // 32-element partials of the block, in element order
   // Long rows (bf16 / float32 with d >= 64, fp8 with d >= 128): the block's
   // four waves sweep the same tiles, so each is loaded once per block into
-  // LDS and every wave reads its B fragment from there.  Tiles go in stages
+  // LDS and every wave reads its sample fragment from there.  Tiles go in stages
   // of kTB; a stage's slot holds its tiles (32 packed rows each, whose
   // 16-byte tails with the weight and per-sample value also shift the rows
   // so that the lanes' 16-byte reads fall in different banks; the tile
@@ -497,17 +597,29 @@ __device__ __forceinline__ void p2_mfma_block(
   // LDS path with bf16 / fp8 operands: one tile's epilogue runs beside the
   // next tile's MFMAs (float32 operands are bound by the MFMA rate)
   constexpr bool kPipe = kLds && P != 0 && DM >= 128;
+  // Accumulator layout.  kT (every path but the pipelined one): samples are
+  // the MFMA rows, a lane's 16 accumulator rows all belong to its element
+  // column, weighted through DPP broadcasts, combined across the two halves.
+  // Pipelined path: elements are the rows and a lane holds one sample column
+  // (its weight a single register), so the tile's sums need no broadcast in
+  // the steps woven around the MFMAs, and are combined across the 32
+  // columns by a transpose-reduction when a cluster ends (over many tiles
+  // at these widths).
+  constexpr bool kT = !kPipe;
   __shared__ __attribute__((aligned(16))) unsigned char ldsS[kLds ? 3 * kSlotB : 16];
   // the LDS byte address of ldsS (the direct loads take LDS addresses)
   const unsigned lds_base = (unsigned)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)ldsS;
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int col = lane & 31;
-  // PB blocks of 32 elements per wave share every B tile
+  // PB blocks of 32 elements per wave share every sample tile
   const int P0 = __builtin_amdgcn_readfirstlane((blk * 4 + (threadIdx.x >> 6)) * 32 * PB);
   const float alpha = M == kCos ? 0.5f : 1.0f;
   const uint32_t lane_off = (uint32_t)((col * C::KP + h * C::HALF) * C::ELEM);  // bytes
-  // the element whose sums this lane ends up holding (twice: lanes l, l^1)
+  // kT: this lane's rows of a tile's per-row values (weights)
+  const int wr = wrow(lane);
+  // element-row layout: the element whose sums this lane ends up holding
+  // (twice: lanes l, l^1)
   const int rr = (lane >> 1) & 15;
   const int prow = 8 * (rr >> 2) + 4 * h + (rr & 3);
 
@@ -562,7 +674,7 @@ __device__ __forceinline__ void p2_mfma_block(
 #pragma unroll
       for (int i = 0; i < C::HALF; ++i) asm volatile("v_accvgpr_write_b32 %0, %1" : "=a"(xr[b][i]) : "v"(xr[b][i]));
     }
-    pout[b] = P0 + 32 * b + prow;
+    pout[b] = P0 + 32 * b + (kT ? col : prow);
     own[b] = labels[pout[b] < n ? pout[b] : n - 1];
     own[b] = (unsigned)own[b] < (unsigned)k ? own[b] : 0;  // labels are checked before; stay in bounds
     w_own[b] = 0.0;
@@ -570,7 +682,11 @@ __device__ __forceinline__ void p2_mfma_block(
   }
 
   AFrag<P, DM> A[PB];
-  float nxc[P == 2 ? PB : 1][16];   // fp8: 64^2 (alpha |x~_q|^2 + u_x) of the 16 C rows
+  // fp8: 64^2 (alpha |x~_q|^2 + u_x) of this lane's element (kT), of its
+  // 16 accumulator rows (element-row layout)
+  float nxc[PB][kT ? 1 : 16];
+  int thrx[PB];   // Euclidean: the element's recompute threshold (float bits, >= 0)
+  bool chk[PB];   // Euclidean: some element of the block may meet the threshold (wave-uniform)
   // The packed cluster blocks are contiguous, so the tile after a cluster's
   // last one is the first tile of the next cluster with samples: it is
   // prefetched there, and a cluster normally starts with its first tile
@@ -581,8 +697,8 @@ __device__ __forceinline__ void p2_mfma_block(
   auto clamp_row = [&](int row) { return row <= last_row ? row : last_row; };
   int pre = -1;
   BFrag<P, DM> b0, b1;
-  float w0 = 0.f, w1 = 0.f;
-  int g0 = -1, g1 = -1;
+  float w0[2] = {0.f, 0.f}, w1[2] = {0.f, 0.f};
+  int g0[2] = {-1, -1}, g1[2] = {-1, -1};
 
   // ---- LDS path: the stage ring.  (cj, cm) is the next stage to load
   // (cluster, stage within it; cj = k past the end, where the last tile is
@@ -654,6 +770,8 @@ __device__ __forceinline__ void p2_mfma_block(
     // rounded to the input precision, plus the augmentation; m is this
     // lane's half of mu_j (in memory, or in the LDS slot of the cluster's
     // first stage)
+    // Euclidean: the squared radius of the cluster's packed sample
+    const float R2 = (M == kEucl && P != 2) ? mu[(size_t)k * C::KP + j] : 0.0f;
     auto buildA = [&](const float* m) {
     float mv[C::HALF];
 #pragma unroll
@@ -674,9 +792,13 @@ __device__ __forceinline__ void p2_mfma_block(
           part = fmaf(v, v, part);  // the norm of the unrounded coordinates
         }
         const float rowv = S2 * fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
-        // the C rows of this lane are elements 8(r/4) + 4h + r%4 of the block
+        if constexpr (kT) {
+          nxc[b][0] = rowv;  // the lane's element is its accumulator column
+        } else {
+          // the C rows of this lane are elements 8(r/4) + 4h + r%4 of the block
 #pragma unroll
-        for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
+          for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
+        }
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
@@ -697,6 +819,8 @@ __device__ __forceinline__ void p2_mfma_block(
           part = __builtin_amdgcn_fdot2_f32_bf16(pk[i2], pk[i2], part, false);
         }
         const float an = fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
+        thrx[b] = __float_as_int(kRecomputeThr<P> * an);
+        chk[b] = __builtin_amdgcn_ballot_w64(an < kSkipFactor<P> * R2) != 0;
         float aug[6];
         split3(an, aug[0], aug[1], aug[2]);
         aug[3] = aug[4] = aug[5] = 1.0f;
@@ -719,6 +843,8 @@ __device__ __forceinline__ void p2_mfma_block(
       // float32: the norm and a 1 ride along as two extra columns
       const float nx = part + __shfl_xor(part, 32, kWave);
       const float an = fmaf(alpha, nx, ux[b]);
+      thrx[b] = __float_as_int(kRecomputeThr<P> * an);
+      chk[b] = __builtin_amdgcn_ballot_w64(an < kSkipFactor<P> * R2) != 0;
       xq[AUG0] = h ? an : xq[AUG0];
       xq[AUG0 + 1] = h ? 1.0f : xq[AUG0 + 1];
 #pragma unroll
@@ -727,59 +853,78 @@ __device__ __forceinline__ void p2_mfma_block(
     };
     if constexpr (!kLds) buildA(mu + (size_t)j * C::KP + h * C::HALF);
 
-    // ---- sweep the cluster's sample tiles (B operand double-buffered: the
-    // next tile's loads are issued before this tile's MFMAs)
+    // ---- sweep the cluster's sample tiles (sample operand double-buffered:
+    // the next tile's loads are issued before this tile's MFMAs)
     const int base = sp_off[j];
     const int ntile = (cnt[j] + 31) >> 5;
     double wsum[PB];
-    float acc[PB][16];
+    constexpr int kNA = kT ? 4 : 16;  // running float32 sums per lane and block
+    float acc[PB][kNA];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       wsum[b] = 0.0;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+      for (int r = 0; r < kNA; ++r) acc[b][r] = 0.f;
     }
     int g = 0;
     // One tile, in four parts: chain (the MFMAs; getB(q) gives step q of
-    // this lane's B fragment, a float2 of two steps for float32, from
+    // this lane's sample fragment, a float2 of two steps for float32, from
     // registers or read from LDS just in time), fixup (pairs prone to
     // cancellation, the cosine self pair), wsum_add (distances and the
-    // weighted sum) and fold (the float64 add every kFold tiles and at the
+    // weighted sums) and fold (the float64 add every kFold tiles and at the
     // cluster's end).  The LDS path overlaps the wsum_add of one tile with
-    // the chain of the next; the arithmetic per pair is the same.
-    auto chain = [&](auto&& getB, int gj, f32x16 (&cc)[PB]) {
+    // the chain of the next; the arithmetic per pair is the same.  wv, gv:
+    // the tile's weights and per-row values as load_tile gives them.
+    auto dist = [&](float c) {
+      if constexpr (M == kEucl)
+        return __builtin_amdgcn_sqrtf(fabsf(c));
+      else
+        return __builtin_amdgcn_fmed3f(c, 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
+    };
+    // fp8: the accumulator starts at 64^2 (element term + sample term), the
+    // MFMA adds -64^2 x~_q . y~_q (unscaled f8f6f4 form, e4m3 operands)
+    auto fp8_init = [&](f32x16& c, int b, const int (&gv)[2]) {
+      if constexpr (kT) {
+        const float v0 = S2 * __int_as_float(gv[0]), v1 = S2 * __int_as_float(gv[1]);
+        static_for<16>([&](auto RC) {
+          constexpr int r = decltype(RC)::value;
+          c[r] = nxc[b][0] + row_val<r>(v0, v1);
+        });
+      } else {
+        const float bcol = S2 * __int_as_float(gv[0]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[r] = nxc[b][r] + bcol;
+      }
+    };
+    auto chain = [&](auto&& getB, const int (&gv)[2], f32x16 (&cc)[PB]) {
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
         f32x16 c;
         if constexpr (P == 0) {
           const float2 b0 = getB(0);
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[0], b0.x, f32x16{}, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[1], b0.y, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(b0.x, A[b].v[0], f32x16{}, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(b0.y, A[b].v[1], c, 0, 0, 0);
 #pragma unroll
           for (int s2 = 1; s2 < C::NSTEP / 2; ++s2) {
             const float2 bq = getB(s2);
-            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2], bq.x, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b].v[2 * s2 + 1], bq.y, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(bq.x, A[b].v[2 * s2], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(bq.y, A[b].v[2 * s2 + 1], c, 0, 0, 0);
           }
         } else if constexpr (P == 1) {
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[0], getB(0), f32x16{}, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(getB(0), A[b].v[0], f32x16{}, 0, 0, 0);
 #pragma unroll
           for (int s = 1; s < C::NSTEP; ++s)
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b].v[s], getB(s), c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(getB(s), A[b].v[s], c, 0, 0, 0);
         } else {
-          // fp8: the accumulator starts at 64^2 (row term + column term), the
-          // MFMA adds -64^2 x~_q . y~_q (unscaled f8f6f4 form, e4m3 operands)
-          const float bcol = S2 * __int_as_float(gj);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) c[r] = nxc[b][r] + bcol;
+          fp8_init(c, b, gv);
 #pragma unroll
           for (int s = 0; s < C::NSTEP; ++s)
-            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[b].v[s], getB(s), c, 0, 0, 0, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(getB(s), A[b].v[s], c, 0, 0, 0, 0, 0, 0);
         }
         cc[b] = c;
       }
     };
-    auto fixup = [&](f32x16 (&cc)[PB], int gj, int srow) {
+    auto fixup = [&](f32x16 (&cc)[PB], const int (&gv)[2], int srow) {
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
         f32x16& c = cc[b];
@@ -789,21 +934,32 @@ __device__ __forceinline__ void p2_mfma_block(
           // The threshold is >= 0, so comparing bit patterns as signed
           // integers orders c like the values (every negative c, -0 included,
           // compares below it): min3 on integers needs no NaN quieting.
+          // kT: the element's threshold, skipped where no pair can meet it;
+          // element rows: the sample's (the lane's column, 6 tau |y~_q|^2,
+          // the same argument with the roles of x~ and y~ exchanged).
+          if constexpr (kT) {
+            if (!chk[b]) continue;  // wave-uniform: no pair of the block can be flagged
+          }
+          const int tx = kT ? thrx[b] : gv[0];
           int mn = __float_as_int(c[0]);
 #pragma unroll
           for (int r = 1; r < 16; ++r) mn = min(mn, __float_as_int(c[r]));
-          if (__builtin_expect(mn < gj, 0)) {
+          if (__builtin_expect(mn < tx, 0)) {
             // one code copy for the flagged rows, taken in turn
             unsigned flagged = 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) flagged |= (__float_as_int(c[r]) < gj ? 1u : 0u) << r;
-            const float* yr = Y32 + (size_t)(srow + col) * DMY;
+            for (int r = 0; r < 16; ++r) flagged |= (__float_as_int(c[r]) < tx ? 1u : 0u) << r;
+            const int e0 = P0 + 32 * b + col;
+            const float* xc = X + (size_t)(e0 < n ? e0 : n - 1) * d;
+            const float* yc = Y32 + (size_t)(srow + col) * DMY;
             while (flagged) {
               const int r = __builtin_ctz(flagged);
               flagged &= flagged - 1;
-              const int e0 = P0 + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3);
-              const int e = e0 < n ? e0 : n - 1;
-              const float* xp = X + (size_t)e * d;
+              // the row's partner: a sample (kT) or an element
+              const int rw = 8 * (r >> 2) + 4 * h + (r & 3);
+              const int er = P0 + 32 * b + rw;
+              const float* xp = kT ? xc : X + (size_t)(er < n ? er : n - 1) * d;
+              const float* yr = kT ? Y32 + (size_t)(srow + rw) * DMY : yc;
               float acc2 = 0.0f;
               for (int q = 0; q < d; ++q) {
                 const float t = xp[q] - yr[q];
@@ -813,107 +969,121 @@ __device__ __forceinline__ void p2_mfma_block(
               for (int q = 0; q < 16; ++q) c[q] = q == r ? acc2 : c[q];
             }
           }
-        } else if constexpr (P != 2) {
-          // cosine: no square root amplifies the expansion's absolute error
-          // (of order 2^-22 here), so only the self pair d(e, e) = 0 is
-          // forced: a column holding one of this block's own 32 elements (in
-          // this lane's half of the rows) zeroes that row.  The unit rows of
-          // both sides are the same product x * rn, so the pair's operands
-          // are identical; zero rows carry id -1 and keep their d = 1.
-          const int self = gj - (P0 + 32 * b);
+        } else if constexpr (P != 2 && !kT) {
+          // cosine, element rows: a column holding one of this block's own
+          // 32 elements (in this lane's half of the rows) zeroes that row
+          // (the self pair, as below)
+          const int self = gv[0] - (P0 + 32 * b);
           if ((unsigned)self < 32u && ((self >> 2) & 1) == h) {
             const int rh = ((self >> 3) << 2) | (self & 3);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
               if (r == rh) c[r] = 0.0f;
           }
+        } else if constexpr (P != 2) {
+          // cosine: no square root amplifies the expansion's absolute error
+          // (of order 2^-22 here), so only the self pair d(e, e) = 0 is
+          // forced: a sample row holding one of this block's own 32 elements
+          // (lane l reads the id of row l % 32) zeroes that row in the
+          // element's column.  The unit rows of both sides are the same
+          // product x * rn, so the pair's operands are identical; zero rows
+          // carry id -1 and keep their d = 1.
+          const int self = gv[0] - (P0 + 32 * b);
+          unsigned hit = (unsigned)__builtin_amdgcn_ballot_w64((unsigned)self < 32u);  // rows 0..31
+          while (__builtin_expect(hit != 0u, 0)) {  // wave-uniform
+            const int sr = __builtin_ctz(hit);
+            hit &= hit - 1u;
+            const int e = __builtin_amdgcn_readlane(self, sr);
+            const int rs = 4 * (sr >> 3) + (sr & 3);
+            const bool mine = col == e && h == ((sr >> 2) & 1);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) c[q] = (mine && q == rs) ? 0.0f : c[q];
+          }
         }
       }
     };
-    auto wsum_add = [&](const f32x16 (&cc)[PB], float wj) {
-      const float wt = P == 2 ? wj * (1.0f / S2) : wj;
+    // (element rows: wv[0] is the weight of the lane's sample column)
+    auto wsum_add = [&](const f32x16 (&cc)[PB], const float (&wv)[2]) {
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
+        float dv[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float dv;
-          if (M == kEucl)
-            dv = __builtin_amdgcn_sqrtf(fabsf(cc[b][r]));
-          else
-            dv = __builtin_amdgcn_fmed3f(cc[b][r], 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
-          acc[b][r] = fmaf(wt, dv, acc[b][r]);
+        for (int r = 0; r < 16; ++r) dv[r] = dist(cc[b][r]);
+        if constexpr (kT) {
+          wsum16(acc[b], wv[0], wv[1], dv);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[b][r] = fmaf(wv[0], dv[r], acc[b][r]);
         }
       }
     };
-    auto fold = [&](bool last) {
-      if (__builtin_expect(++g == kFold || last, 0)) {
+    auto fold = [&](bool last, int tiles = 1) {
+      g += tiles;
+      if (__builtin_expect(g >= kFold<P, kT> || last, 0)) {
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
-          wsum[b] += (double)transpose_reduce16(acc[b], lane);
+          float v;
+          if constexpr (kT)
+            v = lane_sum(acc[b]);
+          else
+            v = transpose_reduce16(acc[b], lane);
+          // fp8: the distances came scaled by 64^2 (a power of two)
+          wsum[b] += P == 2 ? (double)v * (1.0 / S2) : (double)v;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+          for (int r = 0; r < kNA; ++r) acc[b][r] = 0.f;
         }
         g = 0;
       }
     };
-    // The LDS path's chain with the pending tile's wsum_add woven in (one
-    // block of 32 elements per wave there): the B operand is read kAhead
-    // steps ahead of its MFMA, and each step carries a share of the pending
-    // tile's square roots and sums and of the loads of tile tt of the stage
-    // two ahead, issued while the MFMA runs.  Scheduling
-    // barriers keep the steps in this order (left to itself the compiler
-    // reads each step's operand right before its MFMA, which then waits for
-    // the whole LDS latency).  Same arithmetic per accumulator as
-    // chain + wsum_add.
-    auto chain_pipe = [&](auto&& getB, int gj, f32x16 (&cn)[PB], const f32x16 (&cp)[PB], float wp, int tt) {
-      static_assert(PB == 1, "the pipelined LDS path runs one block of 32 elements per wave");
+    // The LDS path's chain with the pending tile's sums woven in (one block
+    // of 32 elements per wave there, element rows): the sample operand is
+    // read kAhead steps ahead of its MFMA, and each step carries a share of
+    // the pending tile's distances and FMAs and of the loads of tile tt of
+    // the stage two ahead, issued while the MFMA runs.  Scheduling barriers
+    // keep the steps in this
+    // order (left to itself the compiler reads each step's operand right
+    // before its MFMA, which then waits for the whole LDS latency).  Same
+    // arithmetic per accumulator as chain + wsum_add.
+    auto chain_pipe = [&](auto&& getB, const int (&gv)[2], f32x16 (&cn)[PB], const f32x16 (&cp)[PB],
+                          const float (&wp)[2], int tt) {
+      static_assert(PB == 1 && !kT, "the pipelined LDS path runs one block of 32 elements per wave, element rows");
       constexpr int NS = C::NSTEP;
       constexpr int kAhead = NS < 4 ? NS : 4;
-      const float wt = P == 2 ? wp * (1.0f / S2) : wp;
       using BT = decltype(getB(0));
       BT bq[kAhead];
 #pragma unroll
       for (int q = 0; q < kAhead; ++q) bq[q] = getB(q);
       f32x16 c;
       if constexpr (P == 2) {
-        const float bcol = S2 * __int_as_float(gj);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) c[r] = nxc[0][r] + bcol;
+        fp8_init(c, 0, gv);
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) c[r] = 0.0f;
       }
       __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int q = 0; q < NS; ++q) {
+      static_for<NS>([&](auto QC) {
+        constexpr int q = decltype(QC)::value;
         const BT cur = bq[q % kAhead];
         if constexpr (P == 1)
           c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0].v[q], cur, c, 0, 0, 0);
         else
           c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[0].v[q], cur, c, 0, 0, 0, 0, 0, 0);
-        if (q + kAhead < NS) bq[q % kAhead] = getB(q + kAhead);
+        if constexpr (q + kAhead < NS) bq[q % kAhead] = getB(q + kAhead);
         // the next-but-one stage's loads of tile tt, spread over the steps
 #pragma unroll
         for (int mi = 0; mi < kDw; ++mi)
           if (q == (2 * mi + 1) * NS / (2 * kDw)) tile_load(tt, mi);
 #pragma unroll
-        for (int r = 16 * q / NS; r < 16 * (q + 1) / NS; ++r) {
-          float dv;
-          if (M == kEucl)
-            dv = __builtin_amdgcn_sqrtf(fabsf(cp[0][r]));
-          else
-            dv = __builtin_amdgcn_fmed3f(cp[0][r], 0.0f, P == 2 ? 2.0f * S2 : 2.0f);
-          acc[0][r] = fmaf(wt, dv, acc[0][r]);
-        }
+        for (int r = 16 * q / NS; r < 16 * (q + 1) / NS; ++r) acc[0][r] = fmaf(wp[0], dist(cp[0][r]), acc[0][r]);
         __builtin_amdgcn_sched_barrier(0);
-      }
+      });
       cn[0] = c;
     };
-    auto tile = [&](auto&& getB, float wj, int gj, int srow, bool last) {
+    auto tile = [&](auto&& getB, const float (&wv)[2], const int (&gv)[2], int srow, bool last) {
       f32x16 cc[PB];
-      chain(getB, gj, cc);
-      fixup(cc, gj, srow);
-      wsum_add(cc, wj);
+      chain(getB, gv, cc);
+      fixup(cc, gv, srow);
+      wsum_add(cc, wv);
       fold(last);
     };
     if constexpr (kLds) {
@@ -921,7 +1091,7 @@ __device__ __forceinline__ void p2_mfma_block(
       // the cluster's first); with two tiles per stage the two accumulator
       // sets swap roles from tile to tile
       f32x16 ca[PB], cb[PB];
-      float wa = 0.0f, wb = 0.0f;
+      float wa[2] = {0.0f, 0.0f}, wb[2] = {0.0f, 0.0f};
       if constexpr (kPipe) {
 #pragma unroll
         for (int b = 0; b < PB; ++b)
@@ -955,24 +1125,46 @@ __device__ __forceinline__ void p2_mfma_block(
             }
           };
         };
-        auto wval = [&](int tt) { return *(const float*)(sb + tt * kTileCh * 16 + col * kLRow + kRowB); };
-        auto gval = [&](int tt) { return *(const int*)(sb + tt * kTileCh * 16 + col * kLRow + kRowB + 4); };
+        // the row tails: weights of rows wr and 16 + wr, per-row values
+        // (element rows: the weight and value of the lane's sample column)
+        auto wval = [&](int tt, float (&wv)[2]) {
+          const unsigned char* tb = sb + tt * kTileCh * 16 + kRowB;
+          if constexpr (kT) {
+            wv[0] = *(const float*)(tb + wr * kLRow);
+            wv[1] = *(const float*)(tb + (wr + 16) * kLRow);
+          } else {
+            wv[0] = *(const float*)(tb + col * kLRow);
+          }
+        };
+        auto gval = [&](int tt, int (&gv)[2]) {
+          const unsigned char* tb = sb + tt * kTileCh * 16 + kRowB + 4;
+          if constexpr (!kT) {
+            gv[0] = *(const int*)(tb + col * kLRow);
+          } else if constexpr (P == 2) {
+            gv[0] = *(const int*)(tb + wr * kLRow);
+            gv[1] = *(const int*)(tb + (wr + 16) * kLRow);
+          } else if constexpr (M == kCos) {
+            gv[0] = *(const int*)(tb + col * kLRow);
+          }
+        };
         if constexpr (kPipe) {
           // a tile's MFMAs and the pending tile's square roots and sums in one
           // stretch of code, so the vector ALU works while the matrix core runs
           {
-            const int g0 = gval(0);
-            chain_pipe(fromLds(0), g0, cb, ca, wa, 0);
+            int gv[2];
+            gval(0, gv);
+            chain_pipe(fromLds(0), gv, cb, ca, wa, 0);
             if (t > 0) fold(false);
-            fixup(cb, g0, base + t * 32);
-            wb = wval(0);
+            fixup(cb, gv, base + t * 32);
+            wval(0, wb);
           }
           if (kTB == 2 && t + 1 < ntile) {  // block-uniform
-            const int g1 = gval(1);
-            chain_pipe(fromLds(1), g1, ca, cb, wb, 1);
+            int gv[2];
+            gval(1, gv);
+            chain_pipe(fromLds(1), gv, ca, cb, wb, 1);
             fold(false);
-            fixup(ca, g1, base + (t + 1) * 32);
-            wa = wval(1);
+            fixup(ca, gv, base + (t + 1) * 32);
+            wval(1, wa);
           } else {
             // one tile in the stage: the pending tile is in cb (and the
             // second tile of the stage two ahead is loaded here)
@@ -982,13 +1174,18 @@ __device__ __forceinline__ void p2_mfma_block(
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) ca[b] = cb[b];
-            wa = wb;
+            wa[0] = wb[0];
           }
         } else {
 #pragma unroll
           for (int tt = 0; tt < kTB; ++tt)
-            if (t + tt < ntile)  // block-uniform
-              tile(fromLds(tt), wval(tt), gval(tt), base + (t + tt) * 32, t + tt + 1 == ntile);
+            if (t + tt < ntile) {  // block-uniform
+              float wv[2];
+              int gv[2];
+              wval(tt, wv);
+              gval(tt, gv);
+              tile(fromLds(tt), wv, gv, base + (t + tt) * 32, t + tt + 1 == ntile);
+            }
         }
         rs = rs == 2 ? 0 : rs + 1;
       }
@@ -1003,25 +1200,25 @@ __device__ __forceinline__ void p2_mfma_block(
       // each tile covers only that tile's loads; an odd last tile runs after
       // the loop from the buffer already loaded, and its successor is loaded
       // into the same buffer once its MFMAs are issued.
-      if (ntile > 0 && pre != base) load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, b0, w0, g0);
+      if (ntile > 0 && pre != base) load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, base, lane_off, col, wr, b0, w0, g0);
       int t = 0;
       for (; t + 2 <= ntile; t += 2) {
-        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, b1, w1, g1);
+        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, base + (t + 1) * 32, lane_off, col, wr, b1, w1, g1);
         tile([&](int q) { return b0.v[q]; }, w0, g0, base + t * 32, false);
         pre = clamp_row(base + (t + 2) * 32);
-        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
+        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, wr, b0, w0, g0);
         tile([&](int q) { return b1.v[q]; }, w1, g1, base + (t + 1) * 32, t + 2 == ntile);
       }
       if (t < ntile) {
         tile([&](int q) { return b0.v[q]; }, w0, g0, base + t * 32, true);
         pre = clamp_row(base + ntile * 32);
-        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, b0, w0, g0);
+        load_tile<M, P, DM>(Ym, w, gid_pk, bnorm, pre, lane_off, col, wr, b0, w0, g0);
       }
     }
     const int sz = csize[j];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
-      if (What != nullptr && pout[b] < n && (lane & 1) == 0) What[(size_t)pout[b] * k + j] = (float)wsum[b];
+      if (What != nullptr && pout[b] < n && (kT ? h == 0 : (lane & 1) == 0)) What[(size_t)pout[b] * k + j] = (float)wsum[b];
       if (j == own[b]) {
         w_own[b] = wsum[b];
       } else if (sz > 0) {
@@ -1040,7 +1237,7 @@ __device__ __forceinline__ void p2_mfma_block(
     const double bb = bmin[b];
     const double mx = a > bb ? a : bb;
     const double s = (szo > 1 && mx > 0.0) ? (bb - a) / mx : 0.0;
-    const bool writer = pout[b] < n && (lane & 1) == 0;
+    const bool writer = pout[b] < n && (kT ? h == 0 : (lane & 1) == 0);
     if (writer) {
       if (a_out) a_out[pout[b]] = (float)a;
       if (b_out) b_out[pout[b]] = (float)bb;
@@ -1160,7 +1357,7 @@ static void launch_jobs_one(hipStream_t st, const P2Job* jobs, const int2* items
 template <int M, int P, int DM>
 static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, const float* w,
                             const int32_t* gid_pk, const int32_t* sp_off, const int32_t* cnt, int k,
-                            const float* mu, int S_pad, void* Ym, float* bnorm) {
+                            float* mu, int S_pad, void* Ym, float* bnorm) {
   hipLaunchKernelGGL((k_pack_mfma<M, P, DM>), dim3((int)ceil_div(S_pad, 256)), dim3(256), 0, st, Y32,
                      aux, w, gid_pk, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
 }
@@ -1216,7 +1413,7 @@ static void launch_pack_one(hipStream_t st, const float* Y32, const float* aux, 
 
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const float* w, const int32_t* gid_pk, const int32_t* sp_off, const int32_t* cnt, int k,
-                      const float* mu, int S_pad, void* Ym, float* bnorm) {
+                      float* mu, int S_pad, void* Ym, float* bnorm) {
   SILH_MFMA_DISPATCH(launch_pack_one, st, Y32, aux, w, gid_pk, sp_off, cnt, k, mu, S_pad, Ym, bnorm);
 }
 

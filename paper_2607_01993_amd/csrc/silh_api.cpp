@@ -604,7 +604,7 @@ silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
     cv.add(&c->aux32, (size_t)c->S_pad).add(&c->Y32, (size_t)c->S_pad * c->DM);
     unsigned char* ym = nullptr;
     if (mfma_pack) {
-      cv.add(&c->mu, (size_t)k * KP).add(&c->bnorm, (size_t)c->S_pad);
+      cv.add(&c->mu, mfma_mu_floats(c->mprec, c->DM, k)).add(&c->bnorm, (size_t)c->S_pad);
       cv.add(&ym, (size_t)c->S_pad * mfma_row_bytes(prec, c->DM));
     }
     CHK(cv.commit(c, c->alloc_sample));

@@ -144,7 +144,7 @@ bool alloc_branch(silh_graph* g, Branch& b) {
             take(g, b.bpart, ceil_div(n, g->p2_rows));
   if (ok && g->mfma) {
     unsigned char* ym = nullptr;
-    ok = take(g, b.mu, k * g->KP) && take(g, b.bnorm, S) && take(g, ym, S * (size_t)mfma_row_bytes(g->mprec, g->DM));
+    ok = take(g, b.mu, mfma_mu_floats(g->mprec, g->DM, k)) && take(g, b.bnorm, S) && take(g, ym, S * (size_t)mfma_row_bytes(g->mprec, g->DM));
     b.Ym = ym;
   }
   if (ok && !g->mfma && phase2_valu_split(g->base.metric, g->DM)) ok = take(g, b.Wpart, n * k);

@@ -147,14 +147,17 @@ bool phase2_valu_split(int metric, int DM);
 // fp8 operands).  prec: 0 float32, 1 bf16, 2 fp8.
 int mfma_kp(int prec, int DM);   // contraction length of a packed row
 int mfma_row_bytes(int prec, int DM);  // bytes per packed row (operands, LDS-path tail)
-// mu: [k][KP] centres, zero beyond DM
+// mu: [k][KP] centres, zero beyond DM, then [k] squared radii of the
+// clusters' packed samples (Euclidean; the largest |y~_q|^2), mfma_mu_floats
+// floats in all
+size_t mfma_mu_floats(int prec, int DM, int k);
 void launch_center(hipStream_t st, const float* Y32, int DM, int KP, const int32_t* sp_off,
                    const int32_t* cnt, int k, float* mu);
 // packs rows [0, min(S_pad, sp_off[k])) (w: weights, gid_pk: element ids of
 // the packed rows, copied into the rows' tails on the LDS path)
 bool launch_pack_mfma(hipStream_t st, int metric, int prec, int DM, const float* Y32, const float* aux,
                       const float* w, const int32_t* gid_pk, const int32_t* sp_off, const int32_t* cnt, int k,
-                      const float* mu, int S_pad, void* Ym, float* bnorm);
+                      float* mu, int S_pad, void* Ym, float* bnorm);
 // elements per float64 partial of the sum of s_hat written by the MFMA
 // Phase-2 kernel (independent of its block shape)
 int phase2_mfma_rows(int prec, int DM);

@@ -97,7 +97,7 @@ void layout(const Shape& s, Slices& sl, Bufs& b) {
   sl.add(&b.p_gid, n).add(&b.gid_view, s.S_cap).add(&b.gid_pk, s.S_cap).add(&b.w32, s.S_cap);
   sl.add(&b.aux32, s.S_cap).add(&b.Y32, s.S_cap * s.DM).add(&b.bpart, ceil_div(n, s.p2_rows));
   if (s.mfma) {
-    sl.add(&b.mu, k * s.KP).add(&b.bnorm, s.S_cap).add(&b.Ym, s.S_cap * (size_t)mfma_row_bytes(s.mprec, s.DM));
+    sl.add(&b.mu, mfma_mu_floats(s.mprec, s.DM, k)).add(&b.bnorm, s.S_cap).add(&b.Ym, s.S_cap * (size_t)mfma_row_bytes(s.mprec, s.DM));
   }
   if (s.split) sl.add(&b.Wpart, n * k);
   if (s.cos) sl.add(&b.rn, n);
