@@ -208,15 +208,19 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
                                                    void* __restrict__ Ym, float* __restrict__ bnorm) {
   using C = MCfg<P, DM>;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S_pad || s >= sp_off[k]) return;  // sp_off[k]: packed rows in use
+  // sp_off[k]: packed rows in use (the Euclidean kernels keep every lane to
+  // the end, for the wave-wide radius below)
+  const bool valid = s < S_pad && s < sp_off[k];
+  if (M != kEucl && !valid) return;
   // cluster of padded row s (binary search over sp_off)
   int lo = 0, hi = k;
-  while (hi - lo > 1) {
+  while (valid && hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (sp_off[mid] <= s) lo = mid; else hi = mid;
   }
   const int j = lo;
-  const bool real = s - sp_off[j] < cnt[j];
+  const bool real = valid && s - sp_off[j] < cnt[j];
+  float ny_r = 0.0f;  // Euclidean: the row's squared norm, 0 for padding
   const float alpha = M == kCos ? 0.5f : 1.0f;
   float row[C::KP];
 #pragma unroll
@@ -260,9 +264,7 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
     }
     const float bn = fmaf(alpha, ny, M == kCos ? aux[s] : 0.0f);
     thr = M == kEucl ? kRecomputeThr<P> * ny : 0.0f;
-    // the cluster's squared radius: the largest ny (>= 0, so its bits order
-    // like the values)
-    if (M == kEucl) atomicMax((int*)(mu + (size_t)k * C::KP + j), __float_as_int(ny));
+    ny_r = ny;
     if (P == 0) {
       row[DM + 1] = bn;
     } else {
@@ -274,20 +276,38 @@ __global__ __launch_bounds__(256) void k_pack_mfma(const float* __restrict__ Y32
   } else {
     row[DM] = row[DM + 1] = row[DM + 2] = 1.0f;
   }
-  bnorm[s] = thr;
-  unsigned char* rowp = (unsigned char*)Ym + (size_t)s * C::ROWB;
-  if constexpr (P == 0) {
-    float* out = (float*)rowp;
+  if (valid) {
+    bnorm[s] = thr;
+    unsigned char* rowp = (unsigned char*)Ym + (size_t)s * C::ROWB;
+    if constexpr (P == 0) {
+      float* out = (float*)rowp;
 #pragma unroll
-    for (int c = 0; c < C::KP; ++c) out[c] = row[c];
-  } else {
-    __bf16* out = (__bf16*)rowp;
+      for (int c = 0; c < C::KP; ++c) out[c] = row[c];
+    } else {
+      __bf16* out = (__bf16*)rowp;
 #pragma unroll
-    for (int c = 0; c < C::KP; ++c) out[c] = (__bf16)row[c];
+      for (int c = 0; c < C::KP; ++c) out[c] = (__bf16)row[c];
+    }
+    if constexpr (C::LDS) {
+      const unsigned g = M == kCos ? (unsigned)gid_pk[s] : __float_as_uint(thr);
+      *(u32x4*)(rowp + C::KP * C::ELEM) = u32x4{__float_as_uint(w[s]), g, 0u, 0u};
+    }
   }
-  if constexpr (C::LDS) {
-    const unsigned g = M == kCos ? (unsigned)gid_pk[s] : __float_as_uint(thr);
-    *(u32x4*)(rowp + C::KP * C::ELEM) = u32x4{__float_as_uint(w[s]), g, 0u, 0u};
+  if constexpr (M == kEucl) {
+    // the cluster's squared radius, the largest ny (>= 0, so its bits order
+    // like the values): one atomic per wave where all its rows belong to one
+    // cluster (rows of a cluster are contiguous), else one per row
+    int* rad = (int*)(mu + (size_t)k * C::KP);
+    const int jv = valid ? j : -1;
+    const int j0 = __builtin_amdgcn_readfirstlane(jv);
+    if (__builtin_amdgcn_ballot_w64(jv != j0) == 0 && j0 >= 0) {
+      int m = __float_as_int(ny_r);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+      if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(rad + j0, m);
+    } else if (real) {
+      atomicMax(rad + j, __float_as_int(ny_r));
+    }
   }
 }
 
