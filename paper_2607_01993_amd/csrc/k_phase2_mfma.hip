@@ -109,6 +109,15 @@ struct MCfg {
   // with the sample's weight and per-sample value (so that one contiguous
   // copy brings a whole tile into LDS)
   static constexpr int ROWB = KP * ELEM + (LDS ? 16 : 0);
+  // bf16: lane half h feeds elements [16 s + 8 h, 16 s + 8 h + 8) of each
+  // 16-wide MFMA step s, so both halves hold DM / 2 coordinates and the
+  // augmentation sits in step DM / 16 (elements 8 s + e of a lane); the other
+  // operand types give each half a contiguous half row [h HALF, (h+1) HALF)
+  static constexpr bool IL = P == 1;
+  static constexpr int FOFF = IL ? 8 : HALF;   // first element of half h: FOFF h
+  static constexpr int FSTEP = IL ? 16 : 8;    // bf16 elements between steps
+  // lane elements that can hold coordinates (the rest: augmentation, zeros)
+  static constexpr int XR = IL ? 8 * ((DM + 15) / 16) : HALF;
 };
 
 int mfma_kp(int prec, int DM) {
@@ -548,7 +557,7 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
   } else {
 #pragma unroll
     for (int s = 0; s < C::NSTEP; ++s)
-      b.v[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 16u * s, 0, 0));
+      b.v[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, lane_off + 2u * C::FSTEP * s, 0, 0));
   }
   wv[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * wr, 0, 0));
   wv[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * (wr + 16u), 0, 0));
@@ -586,9 +595,10 @@ __device__ __forceinline__ void p2_mfma_block(
     float* __restrict__ What, double* __restrict__ bpart, const float* __restrict__ bnorm,
     const float* __restrict__ Y32, int DMY, const float* __restrict__ aux, const float* __restrict__ rn) {
   using C = MCfg<P, DM>;
-  // the augmentation columns always fall in the upper half of the row
+  // contiguous halves: the augmentation columns always fall in the upper half
+  // of the row
   constexpr int AUG0 = DM - C::HALF;
-  static_assert(C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
+  static_assert(C::IL || C::AUG == 0 || (AUG0 >= 0 && AUG0 + C::AUG <= C::HALF), "augmentation placement");
   constexpr float S2 = kFp8Scale * kFp8Scale;
   __shared__ double sh32[4 * PB];  // 32-element partials of the block, in element order
   // Long rows (bf16 / float32 with d >= 64, fp8 with d >= 128): the block's
@@ -635,7 +645,7 @@ __device__ __forceinline__ void p2_mfma_block(
   // PB blocks of 32 elements per wave share every sample tile
   const int P0 = __builtin_amdgcn_readfirstlane((blk * 4 + (threadIdx.x >> 6)) * 32 * PB);
   const float alpha = M == kCos ? 0.5f : 1.0f;
-  const uint32_t lane_off = (uint32_t)((col * C::KP + h * C::HALF) * C::ELEM);  // bytes
+  const uint32_t lane_off = (uint32_t)((col * C::KP + h * C::FOFF) * C::ELEM);  // bytes
   // kT: this lane's rows of a tile's per-row values (weights)
   const int wr = wrow(lane);
   // element-row layout: the element whose sums this lane ends up holding
@@ -666,16 +676,20 @@ __device__ __forceinline__ void p2_mfma_block(
   };
   float ux[PB];
   int pout[PB], own[PB];
-  double w_own[PB], bmin[PB];
+  // b_hat as the fraction bnum / bden of the smallest W_hat_j / |C_j| so far
+  // (candidates compared by cross-multiplication, one division at the end;
+  // bden = 0: none yet)
+  double w_own[PB], bnum[PB], bden[PB];
 #pragma unroll
   for (int b = 0; b < PB; ++b) {
     const int pb = P0 + 32 * b + col;
     const int pa = pb < n ? pb : n - 1;
     const float* xp = X + (size_t)pa * d;
 #pragma unroll
-    for (int i0 = 0; i0 < C::HALF; i0 += V) {
+    for (int i0 = 0; i0 < C::XR; i0 += V) {
       float xc[V];
-      load_chunk<V>(xp, h * C::HALF + i0, d, vec, xc);
+      // lane element i0 is coordinate 16 (i0 / 8) + 8 h + i0 % 8 (bf16)
+      load_chunk<V>(xp, C::IL ? 16 * (i0 / 8) + 8 * h + i0 % 8 : h * C::HALF + i0, d, vec, xc);
 #pragma unroll
       for (int e = 0; e < V; ++e) xr[b][i0 + e] = xc[e];
     }
@@ -686,19 +700,20 @@ __device__ __forceinline__ void p2_mfma_block(
       const float rx = rn[pa];
       ux[b] = rx > 0.f ? 0.f : 0.5f;
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) xr[b][i] *= rx;
+      for (int i = 0; i < C::XR; ++i) xr[b][i] *= rx;
     }
     if constexpr (kXA) {
       // kept in accumulation registers (AGPRs) until the A operands of each
       // cluster read them back
 #pragma unroll
-      for (int i = 0; i < C::HALF; ++i) asm volatile("v_accvgpr_write_b32 %0, %1" : "=a"(xr[b][i]) : "v"(xr[b][i]));
+      for (int i = 0; i < C::XR; ++i) asm volatile("v_accvgpr_write_b32 %0, %1" : "=a"(xr[b][i]) : "v"(xr[b][i]));
     }
     pout[b] = P0 + 32 * b + (kT ? col : prow);
     own[b] = labels[pout[b] < n ? pout[b] : n - 1];
     own[b] = (unsigned)own[b] < (unsigned)k ? own[b] : 0;  // labels are checked before; stay in bounds
     w_own[b] = 0.0;
-    bmin[b] = __builtin_inf();
+    bnum[b] = 1.0;
+    bden[b] = 0.0;
   }
 
   AFrag<P, DM> A[PB];
@@ -795,8 +810,8 @@ __device__ __forceinline__ void p2_mfma_block(
     auto buildA = [&](const float* m) {
     float mv[C::HALF];
 #pragma unroll
-    for (int i0 = 0; i0 < C::HALF; i0 += V) {
-      const fvec t = *(const fvec*)(m + i0);
+    for (int i0 = 0; i0 < C::XR; i0 += V) {
+      const fvec t = *(const fvec*)(m + (C::IL ? 16 * (i0 / 8) + i0 % 8 : i0));
 #pragma unroll
       for (int e = 0; e < V; ++e) mv[i0 + e] = t[e];
     }
@@ -829,14 +844,22 @@ __device__ __forceinline__ void p2_mfma_block(
       }
       if constexpr (P == 1) {
         // bf16: each pair of centred coordinates is rounded into one packed
-        // register (the A fragment's layout) and its squares are added to
-        // the norm by one bf16 dot product (the products are exact in float32)
+        // register (the fragment's layout) and its squares are added to the
+        // norm by one bf16 dot product (the products are exact in float32).
+        // Only the lane elements that can hold coordinates (C::XR) are
+        // formed; the step at DM / 16 carries the augmentation in half
+        // (DM / 8) & 1 (DM = 8 shares step 0: coordinates in half 0)
+        constexpr int kSA = DM / 16, kHA = (DM / 8) & 1;
         bf16x2 pk[C::HALF / 2];
 #pragma unroll
         for (int i2 = 0; i2 < C::HALF / 2; ++i2) {
-          const f32x2 v = {xget(b, 2 * i2) - mv[2 * i2], xget(b, 2 * i2 + 1) - mv[2 * i2 + 1]};
-          pk[i2] = __builtin_convertvector(v, bf16x2);
-          part = __builtin_amdgcn_fdot2_f32_bf16(pk[i2], pk[i2], part, false);
+          if (2 * i2 < C::XR) {
+            const f32x2 v = {xget(b, 2 * i2) - mv[2 * i2], xget(b, 2 * i2 + 1) - mv[2 * i2 + 1]};
+            pk[i2] = __builtin_convertvector(v, bf16x2);
+            part = __builtin_amdgcn_fdot2_f32_bf16(pk[i2], pk[i2], part, false);
+          } else {
+            pk[i2] = bf16x2{};
+          }
         }
         const float an = fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
         thrx[b] = __float_as_int(kRecomputeThr<P> * an);
@@ -844,10 +867,11 @@ __device__ __forceinline__ void p2_mfma_block(
         float aug[6];
         split3(an, aug[0], aug[1], aug[2]);
         aug[3] = aug[4] = aug[5] = 1.0f;
-        // the augmentation columns hold zeros in the upper half's pairs
+        // the augmentation columns hold zeros in the other half's pairs
 #pragma unroll
         for (int q = 0; q < C::AUG; q += 2)
-          pk[(AUG0 + q) / 2] = h ? __builtin_convertvector((f32x2{aug[q], aug[q + 1]}), bf16x2) : pk[(AUG0 + q) / 2];
+          pk[(8 * kSA + q) / 2] =
+              h == kHA ? __builtin_convertvector((f32x2{aug[q], aug[q + 1]}), bf16x2) : pk[(8 * kSA + q) / 2];
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
@@ -871,7 +895,7 @@ __device__ __forceinline__ void p2_mfma_block(
       for (int s = 0; s < C::NSTEP; ++s) A[b].v[s] = xq[s];
     }
     };
-    if constexpr (!kLds) buildA(mu + (size_t)j * C::KP + h * C::HALF);
+    if constexpr (!kLds) buildA(mu + (size_t)j * C::KP + h * C::FOFF);
 
     // ---- sweep the cluster's sample tiles (sample operand double-buffered:
     // the next tile's loads are issued before this tile's MFMAs)
@@ -1131,14 +1155,14 @@ __device__ __forceinline__ void p2_mfma_block(
           issue(rs == 0 ? 2 : rs - 1);
         advance();
         const unsigned char* sb = ldsS + rs * kSlotB;
-        if (t == 0) buildA((const float*)(sb + kMuOff) + h * C::HALF);
+        if (t == 0) buildA((const float*)(sb + kMuOff) + h * C::FOFF);
         auto fromLds = [&](int tt) {
-          const unsigned char* tl = sb + tt * kTileCh * 16 + col * kLRow + h * C::HALF * C::ELEM;
+          const unsigned char* tl = sb + tt * kTileCh * 16 + col * kLRow + h * C::FOFF * C::ELEM;
           return [tl](int q) {
             if constexpr (P == 0) {
               return *(const float2*)(tl + 8 * q);
             } else if constexpr (P == 1) {
-              return *(const bf16x8*)(tl + 16 * q);
+              return *(const bf16x8*)(tl + 2 * C::FSTEP * q);
             } else {
               const u32x4 lo = *(const u32x4*)(tl + 32 * q), hi = *(const u32x4*)(tl + 32 * q + 16);
               return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
@@ -1236,14 +1260,15 @@ __device__ __forceinline__ void p2_mfma_block(
       }
     }
     const int sz = csize[j];
+    const double dsz = (double)sz;
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       if (What != nullptr && pout[b] < n && (kT ? h == 0 : (lane & 1) == 0)) What[(size_t)pout[b] * k + j] = (float)wsum[b];
       if (j == own[b]) {
         w_own[b] = wsum[b];
-      } else if (sz > 0) {
-        const double bj = wsum[b] / (double)sz;
-        bmin[b] = bj < bmin[b] ? bj : bmin[b];
+      } else if (sz > 0 && wsum[b] * bden[b] < bnum[b] * dsz) {
+        bnum[b] = wsum[b];
+        bden[b] = dsz;
       }
     }
   }
@@ -1254,7 +1279,7 @@ __device__ __forceinline__ void p2_mfma_block(
   for (int b = 0; b < PB; ++b) {
     const int szo = csize[own[b]];
     const double a = szo > 1 ? w_own[b] / (double)(szo - 1) : 0.0;
-    const double bb = bmin[b];
+    const double bb = bden[b] > 0.0 ? bnum[b] / bden[b] : __builtin_inf();
     const double mx = a > bb ? a : bb;
     const double s = (szo > 1 && mx > 0.0) ? (bb - a) / mx : 0.0;
     const bool writer = pout[b] < n && (kT ? h == 0 : (lane & 1) == 0);
