@@ -721,7 +721,7 @@ __device__ __forceinline__ void p2_mfma_block(
   // 16 accumulator rows (element-row layout)
   float nxc[PB][kT ? 1 : 16];
   int thrx[PB];   // Euclidean: the element's recompute threshold (float bits, >= 0)
-  bool chk[PB];   // Euclidean: some element of the block may meet the threshold (wave-uniform)
+  int chk[PB];    // Euclidean: some element of the block may meet the threshold (wave-uniform, 0 / 1)
   // The packed cluster blocks are contiguous, so the tile after a cluster's
   // last one is the first tile of the next cluster with samples: it is
   // prefetched there, and a cluster normally starts with its first tile
@@ -863,7 +863,7 @@ __device__ __forceinline__ void p2_mfma_block(
         }
         const float an = fmaf(alpha, part + __shfl_xor(part, 32, kWave), ux[b]);
         thrx[b] = __float_as_int(kRecomputeThr<P> * an);
-        chk[b] = __builtin_amdgcn_ballot_w64(an < kSkipFactor<P> * R2) != 0;
+        chk[b] = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_ballot_w64(an < kSkipFactor<P> * R2) != 0 ? 1 : 0);
         float aug[6];
         split3(an, aug[0], aug[1], aug[2]);
         aug[3] = aug[4] = aug[5] = 1.0f;
@@ -888,7 +888,7 @@ __device__ __forceinline__ void p2_mfma_block(
       const float nx = part + __shfl_xor(part, 32, kWave);
       const float an = fmaf(alpha, nx, ux[b]);
       thrx[b] = __float_as_int(kRecomputeThr<P> * an);
-      chk[b] = __builtin_amdgcn_ballot_w64(an < kSkipFactor<P> * R2) != 0;
+      chk[b] = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_ballot_w64(an < kSkipFactor<P> * R2) != 0 ? 1 : 0);
       xq[AUG0] = h ? an : xq[AUG0];
       xq[AUG0 + 1] = h ? 1.0f : xq[AUG0 + 1];
 #pragma unroll
@@ -982,7 +982,7 @@ __device__ __forceinline__ void p2_mfma_block(
           // element rows: the sample's (the lane's column, 6 tau |y~_q|^2,
           // the same argument with the roles of x~ and y~ exchanged).
           if constexpr (kT) {
-            if (!chk[b]) continue;  // wave-uniform: no pair of the block can be flagged
+            if (__builtin_amdgcn_readfirstlane(chk[b]) == 0) continue;  // wave-uniform: no pair of the block can be flagged
           }
           const int tx = kT ? thrx[b] : gv[0];
           int mn = __float_as_int(c[0]);
