@@ -234,28 +234,6 @@ void launch_sample_sizes(hipStream_t st, const int32_t* s_off, int k, int s_cap,
   hipLaunchKernelGGL(k_sample_sizes, dim3(1), dim3(1024), 0, st, s_off, k, s_cap, cnt, sp_off, status);
 }
 
-// Clear the packed rows in use, [0, min(*used, cap)): id -1, weight 0, aux 0,
-// coordinates 0 (what the padding rows must hold).
-__global__ __launch_bounds__(256) void k_clear_rows(const int32_t* __restrict__ used, int cap, int DM,
-                                                    int32_t* __restrict__ gid_pk, float* __restrict__ w32,
-                                                    float* __restrict__ aux32, float* __restrict__ Y32) {
-  const int64_t rows = *used < cap ? *used : cap;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
-    gid_pk[r] = -1;
-    w32[r] = 0.0f;
-    aux32[r] = 0.0f;
-  }
-  const int64_t ny = rows * DM;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ny; i += (int64_t)gridDim.x * 256) Y32[i] = 0.0f;
-}
-
-void launch_clear_rows(hipStream_t st, const int32_t* used, int cap, int DM, int32_t* gid_pk, float* w32,
-                       float* aux32, float* Y32) {
-  const int64_t blocks = ceil_div((int64_t)cap * DM, 256);
-  hipLaunchKernelGGL(k_clear_rows, dim3((int)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, st, used, cap, DM,
-                     gid_pk, w32, aux32, Y32);
-}
-
 __global__ void k_put_status(const int* __restrict__ status, int32_t* __restrict__ out) { *out = *status; }
 
 int64_t dist_capacity(int64_t n, double lnterm) {

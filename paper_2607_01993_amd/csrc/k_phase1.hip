@@ -656,7 +656,7 @@ void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, 
 __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
                                               const int32_t* __restrict__ slab,
                                               const int32_t* __restrict__ flag,
-                                              const int32_t* __restrict__ pos, int n,
+                                              const int32_t* __restrict__ pos, int n, int k,
                                               const float* __restrict__ X, int d, int DM,
                                               const double* __restrict__ p_gid,
                                               const int32_t* __restrict__ s_off,
@@ -666,7 +666,22 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
                                               int32_t* __restrict__ gid_pk, float* __restrict__ w32,
                                               float* __restrict__ aux32, float* __restrict__ Y32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !flag[i]) return;
+  if (i >= n) {
+    // threads past n: the padding rows of each cluster block (at most 31,
+    // slot (i - n) % 32 of cluster (i - n) / 32), id -1 and all zeros, so no
+    // clear of the packed arrays is needed
+    const int t = i - n, j = t >> 5;
+    if (j >= k) return;
+    const int dst = sp_off[j] + (s_off[j + 1] - s_off[j]) + (t & 31);
+    if (dst >= sp_off[j + 1] || dst >= cap) return;
+    gid_pk[dst] = -1;
+    w32[dst] = 0.0f;
+    aux32[dst] = 0.0f;
+    float* yr = Y32 + (size_t)dst * DM;
+    for (int c = 0; c < DM; c += 4) *(float4*)(yr + c) = float4{0.f, 0.f, 0.f, 0.f};
+    return;
+  }
+  if (!flag[i]) return;
   const int g = perm[i];
   const int j = slab[i];
   const int ps = pos[i];
@@ -683,10 +698,8 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
   // cosine: the row times its float32 reciprocal norm, the same product the
   // Phase-2 kernels form for the element side (identical rows stay identical)
   float scale = 1.0f;
-  if (mode == 1) {
-    scale = rn[g];
-    aux32[dst] = scale > 0.0f ? 0.0f : 0.5f;
-  }
+  if (mode == 1) scale = rn[g];
+  aux32[dst] = (mode == 1 && !(scale > 0.0f)) ? 0.5f : 0.0f;
   if (vec) {
     // 16-byte row chunks (DM is a multiple of 8)
     for (int c = 0; c < DM; c += 4) {
@@ -727,12 +740,13 @@ void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn) {
 }
 
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
-                 const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
+                 const int32_t* pos, int n, int k, const float* X, int d, int DM, const double* p_gid,
                  const int32_t* s_off, const int32_t* sp_off, int mode, const float* rn, int cap,
                  int64_t* gid_view,
                  int32_t* gid_pk, float* w32, float* aux32, float* Y32) {
-  hipLaunchKernelGGL(k_pack, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, perm, slab, flag, pos, n,
-                     X, d, DM, p_gid, s_off, sp_off, mode, rn, cap, gid_view, gid_pk, w32, aux32, Y32);
+  hipLaunchKernelGGL(k_pack, dim3((int)ceil_div((int64_t)n + 32 * (int64_t)k, 256)), dim3(256), 0, st, perm, slab,
+                     flag, pos, n, k, X, d, DM, p_gid, s_off, sp_off, mode, rn, cap, gid_view, gid_pk, w32, aux32,
+                     Y32);
 }
 
 // ----------------------------------------------------------------------------

@@ -398,31 +398,75 @@ silh_status h2d(silh_ctx* c, T* dst, const std::vector<T>& src) {
   return SILH_OK;
 }
 
+// Two uploads in one copy when dst_b is the next slot of the same carve
+// (dst_a's span rounded up to 256 bytes): the padding between them is staged
+// as zeros.  Each copy is a transfer of its own on the stream, so adjacent
+// small arrays go together.
+template <class A, class B>
+silh_status h2d_pair(silh_ctx* c, A* dst_a, const std::vector<A>& a, B* dst_b, const std::vector<B>& b) {
+  const size_t na = a.size() * sizeof(A), nb = b.size() * sizeof(B);
+  const size_t gap = (size_t)((const char*)dst_b - (const char*)dst_a);
+  if (na == 0 || nb == 0 || gap != Carve::span(na)) {
+    CHK(h2d(c, dst_a, a));
+    return h2d(c, dst_b, b);
+  }
+  void* p = nullptr;
+  CHK(stage(c, gap + nb, &p));
+  std::memcpy(p, a.data(), na);
+  std::memset((char*)p + na, 0, gap - na);
+  std::memcpy((char*)p + gap, b.data(), nb);
+  HIPCHK(hipMemcpyAsync(dst_a, p, gap + nb, hipMemcpyHostToDevice, c->st));
+  return SILH_OK;
+}
+
 // Device-to-host read-backs: every part is copied through the staging block,
-// then the stream is synchronised and the values land in host memory.
+// then the stream is synchronised and the values land in host memory.  Parts
+// that lie within 512 bytes of each other on the device (slots of one carve)
+// are copied as one span.
 struct Fetch {
   void* host;
   const void* dev;
   size_t bytes;
 };
 silh_status fetch(silh_ctx* c, std::initializer_list<Fetch> parts) {
+  std::vector<Fetch> ps(parts);
+  std::sort(ps.begin(), ps.end(), [](const Fetch& x, const Fetch& y) { return x.dev < y.dev; });
+  // runs of parts copied together: [first part, last part]
+  std::vector<std::pair<size_t, size_t>> runs;
+  for (size_t i = 0; i < ps.size(); ++i) {
+    if (!runs.empty()) {
+      const Fetch& last = ps[runs.back().second];
+      const char* end = (const char*)last.dev + last.bytes;
+      if ((const char*)ps[i].dev >= end && (const char*)ps[i].dev - end <= 512) {
+        runs.back().second = i;
+        continue;
+      }
+    }
+    runs.push_back({i, i});
+  }
   size_t total = 0;
-  for (const Fetch& f : parts) total += (f.bytes + 255) / 256 * 256;
+  for (const auto& r : runs)
+    total += ((size_t)((const char*)ps[r.second].dev + ps[r.second].bytes - (const char*)ps[r.first].dev) + 255) / 256 * 256;
   if (!c->pin || c->pin_used + total > c->pin_size) {
     HIPCHK(hipStreamSynchronize(c->st));
     c->pin_used = 0;
     if (!c->pin || total > c->pin_size) CHK(pin_acquire(c, total));
   }
   std::vector<void*> slots;
-  for (const Fetch& f : parts) {
+  for (const auto& r : runs) {
+    const char* lo = (const char*)ps[r.first].dev;
+    const size_t span = (size_t)((const char*)ps[r.second].dev + ps[r.second].bytes - lo);
     void* p = nullptr;
-    CHK(stage(c, f.bytes, &p));
-    HIPCHK(hipMemcpyAsync(p, f.dev, f.bytes, hipMemcpyDeviceToHost, c->st));
+    CHK(stage(c, span, &p));
+    HIPCHK(hipMemcpyAsync(p, lo, span, hipMemcpyDeviceToHost, c->st));
     slots.push_back(p);
   }
   HIPCHK(hipStreamSynchronize(c->st));
-  size_t i = 0;
-  for (const Fetch& f : parts) std::memcpy(f.host, slots[i++], f.bytes);
+  for (size_t ri = 0; ri < runs.size(); ++ri) {
+    const char* lo = (const char*)ps[runs[ri].first].dev;
+    for (size_t i = runs[ri].first; i <= runs[ri].second; ++i)
+      std::memcpy(ps[i].host, (const char*)slots[ri] + ((const char*)ps[i].dev - lo), ps[i].bytes);
+  }
   c->pin_used = 0;  // every copy of this context is complete
   return SILH_OK;
 }
@@ -516,8 +560,7 @@ silh_status build_index(silh_ctx* c) {
       c->q_h[j] = qj < 1.0 ? qj : 1.0;
     }
   }
-  CHK(h2d(c, c->off, c->off_h));
-  CHK(h2d(c, c->q, c->q_h));
+  CHK(h2d_pair(c, c->off, c->off_h, c->q, c->q_h));
   {
     Launch L(c, K_SORT_SCATTER);
     launch_scatter(c->st, c->labels, n, k, seg, c->uh, c->off, c->perm, c->slab);
@@ -610,14 +653,11 @@ silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
     CHK(cv.commit(c, c->alloc_sample));
     c->Ym = ym;
   }
-  CHK(h2d(c, c->sp_off, c->sp_off_h));
-  CHK(h2d(c, c->cnt, c->cnt_h));
-  HIPCHK(hipMemsetAsync(c->gid_pk, 0xFF, (size_t)c->S_pad * sizeof(int32_t), c->st));
-  // w32, aux32 and Y32 are consecutive in the stage's allocation: one clear
-  HIPCHK(hipMemsetAsync(c->w32, 0, (size_t)((char*)(c->Y32 + (size_t)c->S_pad * c->DM) - (char*)c->w32), c->st));
+  CHK(h2d_pair(c, c->sp_off, c->sp_off_h, c->cnt, c->cnt_h));
+  // every packed row, padding included, is written by k_pack (no clears)
   {
     Launch L(c, K_PACK);
-    launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, c->X, c->d, c->DM, c->p_gid, c->s_off,
+    launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, k, c->X, c->d, c->DM, c->p_gid, c->s_off,
                 c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, c->rn, (int)c->S_pad, c->gid_view, c->gid_pk,
                 c->w32, c->aux32, c->Y32);
     CHK(L.done());
@@ -647,7 +687,6 @@ silh_status sample_stage_buffers(silh_ctx* c) {
   c->f0_cl = c->items = c->citem_first = c->citem_count = c->gid_pk = c->imeta = nullptr;
   c->ibase = c->dbase = nullptr;
   c->dkeep = nullptr;
-  c->p1_status = nullptr;
   c->f0X = c->W0 = c->partial = nullptr;
   c->w32 = c->aux32 = c->Y32 = c->mu = c->bnorm = nullptr;
   c->Ym = nullptr;
@@ -655,7 +694,8 @@ silh_status sample_stage_buffers(silh_ctx* c) {
   const int nb = (int)ceil_div(n, c->p2_rows);
   Carve cv;
   cv.add(&c->flag, (size_t)n).add(&c->pos, (size_t)n + 1).add(&c->scan_tmp, (size_t)ceil_div(n, kScanTile) + 1);
-  cv.add(&c->p_gid, (size_t)n).add(&c->f0_off, (size_t)k + 1).add(&c->s_off, (size_t)k + 1);
+  // f0_off, s_off and the Phase-1 status are read back together (one copy)
+  cv.add(&c->p_gid, (size_t)n).add(&c->f0_off, (size_t)k + 1).add(&c->s_off, (size_t)k + 1).add(&c->p1_status, 1);
   cv.add(&c->sp_off, (size_t)k + 1).add(&c->cnt, (size_t)k).add(&c->bpart, (size_t)nb).add(&c->mean_d, 1);
   return cv.commit(c, c->alloc_sample);
 }
@@ -704,7 +744,7 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
       cv.add(&c->f0_gid, (size_t)f0_cap).add(&c->f0_cl, (size_t)f0_cap).add(&c->f0X, (size_t)f0_cap * c->DM);
       cv.add(&c->W0, (size_t)f0_cap).add(&c->items, (size_t)items_cap * 6).add(&c->citem_first, (size_t)k);
       cv.add(&c->citem_count, (size_t)k).add(&c->partial, (size_t)part_cap).add(&c->ibase, (size_t)k);
-      cv.add(&c->imeta, 2).add(&c->p1_status, 1);
+      cv.add(&c->imeta, 2);
       if (dist_cap > 0) cv.add(&c->dbase, (size_t)k).add(&c->dkeep, (size_t)dist_cap);
       CHK(cv.commit(c, c->alloc_sample));
     }

@@ -76,9 +76,11 @@ void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, 
 void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn);
 // Scatter the selected elements into the cluster-blocked, padded sample.
 // mode 0: raw coordinates; 1: rows times rn (unit L2 norm, cosine).  Rows at
-// or past `cap` (the capacity of the packed arrays) are not written.
+// or past `cap` (the capacity of the packed arrays) are not written.  Every
+// other row in [0, sp_off[k]) is written, the padding rows of each cluster
+// block as id -1 with zero weight, aux and coordinates: no prior clear.
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
-                 const int32_t* pos, int n, const float* X, int d, int DM, const double* p_gid,
+                 const int32_t* pos, int n, int k, const float* X, int d, int DM, const double* p_gid,
                  const int32_t* s_off, const int32_t* sp_off, int mode, const float* rn, int cap,
                  int64_t* gid_view, int32_t* gid_pk, float* w32, float* aux32, float* Y32);
 
@@ -203,9 +205,6 @@ int64_t dist_capacity(int64_t n, double lnterm);
 // cnt[j] = |F_j|, sp_off = offsets of the blocks padded to kSamplePad rows
 void launch_sample_sizes(hipStream_t st, const int32_t* s_off, int k, int s_cap, int32_t* cnt, int32_t* sp_off,
                          int* status);
-// gid_pk = -1, w32 = aux32 = 0, Y32 = 0 over rows [0, min(*used, cap))
-void launch_clear_rows(hipStream_t st, const int32_t* used, int cap, int DM, int32_t* gid_pk, float* w32,
-                       float* aux32, float* Y32);
 void launch_put_status(hipStream_t st, const int* status, int32_t* out);
 
 // ---- host-side helpers shared by the C-ABI files ----------------------------
