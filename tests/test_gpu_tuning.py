@@ -22,7 +22,7 @@ def _run(X, L, k, metric, prec, mode):
 
 @pytest.mark.parametrize("metric,prec,d", [("eucl", "fp32", 32), ("eucl", "bf16", 64), ("cos", "bf16", 16),
                                            ("cos", "fp32", 64), ("eucl", "bf16", 5), ("eucl", "bf16", 128),
-                                           ("cos", "fp8", 128), ("eucl", "bf16", 32), ("cos", "fp8", 64)])
+                                           ("cos", "fp8", 128), ("eucl", "bf16", 32)])
 def test_block_shapes_agree_bitwise(metric, prec, d):
     X, L = synth.tiny_case(7000, d, 5, seed=81)
     Xd, Ld = dev(X, L)
