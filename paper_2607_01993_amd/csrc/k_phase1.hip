@@ -699,16 +699,26 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
   // Phase-2 kernels form for the element side (identical rows stay identical)
   float scale = 1.0f;
   if (mode == 1) scale = rn[g];
-  aux32[dst] = (mode == 1 && !(scale > 0.0f)) ? 0.5f : 0.0f;
+  // Canberra (mode 2): whether the row has a coordinate outside [-2^62, 2^62]
+  // or not finite (a failed <= test), which keeps the Phase-2 kernel on its
+  // per-coordinate form for this sample
+  bool big = false;
   if (vec) {
     // 16-byte row chunks (DM is a multiple of 8)
     for (int c = 0; c < DM; c += 4) {
       const float4 v = c < d ? *(const float4*)(xr + c) : float4{0.f, 0.f, 0.f, 0.f};
       *(float4*)(yr + c) = float4{v.x * scale, v.y * scale, v.z * scale, v.w * scale};
+      big = big || !(fabsf(v.x) <= 0x1p62f && fabsf(v.y) <= 0x1p62f && fabsf(v.z) <= 0x1p62f &&
+                     fabsf(v.w) <= 0x1p62f);
     }
   } else {
-    for (int c = 0; c < DM; ++c) yr[c] = c < d ? xr[c] * scale : 0.0f;
+    for (int c = 0; c < DM; ++c) {
+      const float v = c < d ? xr[c] : 0.0f;
+      yr[c] = v * scale;
+      big = big || !(fabsf(v) <= 0x1p62f);
+    }
   }
+  aux32[dst] = (mode == 1 && !(scale > 0.0f)) ? 0.5f : (mode == 2 && big) ? 1.0f : 0.0f;
 }
 
 // Reciprocal L2 norm of every row in float32 (one rounding per operation:

@@ -25,9 +25,16 @@ constexpr int kGroup = 32;  // samples summed in float32 before the float64 add
 // else 0): for unit x_hat, y_hat, 1 - x_hat.y_hat = |x_hat - y_hat|^2 / 2, and
 // the u terms give 1 whenever either vector is zero; this form does not
 // cancel for near-parallel pairs.
-// Canberra's guard (G) keeps a 0/0 coordinate at 0 (den >= FLT_MIN); without
-// it the step is one instruction shorter, valid when |x_c| >= FLT_MIN for
-// every coordinate of the element row (then den > 0 whatever y is).
+// Canberra's guard (G) keeps a 0/0 coordinate at 0 (den >= FLT_MIN).  The
+// unguarded form (dist32 with G = false) takes the coordinates in pairs with
+// one reciprocal per pair,
+//   |x0 - y0| / a + |x1 - y1| / b = (|x0 - y0| b + |x1 - y1| a) / (a b),
+// a = |x0| + |y0|, b = |x1| + |y1|: the reciprocal is the costly instruction
+// (measured at several times an FMA's issue cost), the pair form has one per
+// two coordinates for three more multiplies.  It is valid when every
+// coordinate of the element row lies in [2^-62, 2^62] in magnitude and every
+// coordinate of the sample row in [0, 2^62]: then a, b lie in [2^-62, 2^63],
+// a b is a normal float, the numerator is at most 2 a b, and no 0/0 arises.
 template <int M, bool G = true>
 __device__ __forceinline__ float dist32_step(float s, float xc, float yc) {
   if (M == kManh) return s + fabsf(xc - yc);
@@ -51,6 +58,16 @@ template <int M, int DM, bool G = true>
 __device__ __forceinline__ float dist32(const float (&x)[DM], const float* __restrict__ y, float ux,
                                       float uy) {
   float s = 0.f;
+  if constexpr (M == kCanb && !G) {
+    static_assert(DM % 2 == 0, "coordinate pairs");
+#pragma unroll
+    for (int c = 0; c < DM; c += 2) {
+      const float a = fabsf(x[c]) + fabsf(y[c]), b = fabsf(x[c + 1]) + fabsf(y[c + 1]);
+      const float num = fmaf(fabsf(x[c] - y[c]), b, fabsf(x[c + 1] - y[c + 1]) * a);
+      s = fmaf(num, __builtin_amdgcn_rcpf(a * b), s);
+    }
+    return s;
+  }
 #pragma unroll
   for (int c = 0; c < DM; ++c) s = dist32_step<M, G>(s, x[c], y[c]);
   return dist32_final<M>(s, ux, uy);
@@ -100,15 +117,17 @@ __device__ __forceinline__ void p2_valu_block(
   }
   const int own = (unsigned)labels[er] < (unsigned)k ? labels[er] : 0;  // labels are checked before; stay in bounds
 
-  // Canberra: the guard-free step when no element row of the wave has a
-  // coordinate below FLT_MIN in magnitude (padding coordinates are 0, so a
-  // padded row keeps the guard)
+  // Canberra: the pair form (dist32, G = false) when every element row of the
+  // wave has its coordinates in [2^-62, 2^62] in magnitude (padding
+  // coordinates are 0, so a padded row keeps the guarded form), and for each
+  // sample whose row the packing did not flag (aux = 1: a coordinate past
+  // 2^62 or not finite)
   bool guard = true;
   if (M == kCanb) {
-    bool nz = true;
+    bool in = true;
 #pragma unroll
-    for (int c = 0; c < DM; ++c) nz = nz && fabsf(x[c]) >= FLT_MIN;
-    guard = !__all(nz);
+    for (int c = 0; c < DM; ++c) in = in && fabsf(x[c]) >= 0x1p-62f && fabsf(x[c]) <= 0x1p62f;
+    guard = !__all(in);
   }
   double w_own = 0.0;
   double bmin = __builtin_inf();
@@ -124,7 +143,10 @@ __device__ __forceinline__ void p2_valu_block(
         for (int q = g0; q < g1; ++q) {
           const float* y = Y + (size_t)(s0 + q) * ystride + c0;
           const float uy = M == kCos ? aux[s0 + q] : 0.f;
-          acc = fmaf(w[s0 + q], dist32<M, DM, G>(x, y, ux, uy), acc);
+          if (M == kCanb && !G && aux[s0 + q] != 0.f)  // wave-uniform
+            acc = fmaf(w[s0 + q], dist32<M, DM, true>(x, y, ux, uy), acc);
+          else
+            acc = fmaf(w[s0 + q], dist32<M, DM, G>(x, y, ux, uy), acc);
         }
         accd += (double)acc;
       }

@@ -658,7 +658,7 @@ silh_status compact_and_pack(silh_ctx* c, bool* overflow) {
   {
     Launch L(c, K_PACK);
     launch_pack(c->st, c->perm, c->slab, c->flag, c->pos, n, k, c->X, c->d, c->DM, c->p_gid, c->s_off,
-                c->sp_off, c->prm.metric == SILH_COS ? 1 : 0, c->rn, (int)c->S_pad, c->gid_view, c->gid_pk,
+                c->sp_off, pack_mode(c->prm.metric), c->rn, (int)c->S_pad, c->gid_view, c->gid_pk,
                 c->w32, c->aux32, c->Y32);
     CHK(L.done());
   }

@@ -200,7 +200,7 @@ bool enqueue(silh_graph* g, Branch& b, int i) {
   launch_gather_at(st, b.pos, b.off, k, b.s_off);
   launch_sample_sizes(st, b.s_off, k, (int)g->S_cap, b.cnt, b.sp_off, b.status);
   launch_pack(st, b.perm, b.slab, b.flag, b.pos, n, k, g->X, d, DM, b.p_gid, b.s_off, b.sp_off,
-              metric == SILH_COS ? 1 : 0, g->rn, (int)g->S_cap, b.gid_view, b.gid_pk, b.w32, b.aux32, b.Y32);
+              pack_mode(metric), g->rn, (int)g->S_cap, b.gid_view, b.gid_pk, b.w32, b.aux32, b.Y32);
   // Phase 2 and the mean (the block shape does not change the results)
   P2Args A;
   A.X = g->X;

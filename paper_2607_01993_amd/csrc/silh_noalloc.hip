@@ -173,7 +173,7 @@ extern "C" silh_status silh_exact_noalloc(const silh_params* prm, const float* X
   launch_scan(st, B.flag, n, B.pos, B.scan_tmp);
   launch_gather_at(st, B.pos, B.off, k, B.s_off);
   launch_sample_sizes(st, B.s_off, k, (int)sh.S_cap, B.cnt, B.sp_off, B.status);
-  launch_pack(st, B.perm, B.slab, B.flag, B.pos, n, k, X, d, DM, B.p_gid, B.s_off, B.sp_off, metric == SILH_COS ? 1 : 0,
+  launch_pack(st, B.perm, B.slab, B.flag, B.pos, n, k, X, d, DM, B.p_gid, B.s_off, B.sp_off, pack_mode(metric),
               B.rn, (int)sh.S_cap, B.gid_view, B.gid_pk, B.w32, B.aux32, B.Y32);
   P2Args A;
   A.X = X;
