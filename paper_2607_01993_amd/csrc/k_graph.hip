@@ -105,7 +105,7 @@ __global__ __launch_bounds__(1024) void k_f0_items(const int32_t* __restrict__ c
                                                    int32_t* __restrict__ citem_count,
                                                    int64_t* __restrict__ ibase, int32_t* __restrict__ meta,
                                                    int* __restrict__ status, int64_t* __restrict__ dbase,
-                                                   int64_t dist_cap) {
+                                                   int64_t dist_cap, bool assign) {
   __shared__ int64_t part[1024];
   __shared__ int over;
   if (threadIdx.x == 0) over = f0_off[k] > f0_cap;
@@ -144,8 +144,11 @@ __global__ __launch_bounds__(1024) void k_f0_items(const int32_t* __restrict__ c
   if (threadIdx.x == 0) {
     meta[1] = (dbase != nullptr && !drop && nd_tot <= dist_cap) ? 1 : 0;
     meta[0] = drop ? 0 : (int32_t)ni_tot;
-    if (over) *status |= kStatusF0;
-    if (drop) *status |= kStatusPartial;
+    const int bits = (over ? kStatusF0 : 0) | (drop ? kStatusPartial : 0);
+    if (assign)
+      *status = bits;
+    else if (bits)
+      *status |= bits;
   }
 }
 
@@ -195,9 +198,9 @@ __global__ __launch_bounds__(256) void k_items_fill(const int32_t* __restrict__ 
 void launch_f0_items(hipStream_t st, const int32_t* csize, const int32_t* off, int32_t* f0_off, int k,
                      int64_t t, int chunk, int f0_cap, int64_t part_cap, int items_cap, int32_t* citem_first,
                      int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status,
-                     int64_t* dbase, int64_t dist_cap) {
+                     int64_t* dbase, int64_t dist_cap, bool assign_status) {
   hipLaunchKernelGGL(k_f0_items, dim3(1), dim3(1024), 0, st, csize, f0_off, k, t, chunk, f0_cap, part_cap,
-                     citem_first, citem_count, ibase, meta, status, dbase, dist_cap);
+                     citem_first, citem_count, ibase, meta, status, dbase, dist_cap, assign_status);
   hipLaunchKernelGGL(k_items_fill, dim3((int)ceil_div(items_cap, 256)), dim3(256), 0, st, off, f0_off,
                      citem_first, ibase, meta, k, chunk, items_cap, items);
 }

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(64) void k_unit_hist(const int32_t* __restrict__ la
     else
       anybad = 1;
   }
-  if (anybad) atomicOr(bad, 1);
+  if (anybad && bad != nullptr) atomicOr(bad, 1);
   __syncthreads();
   const int units = gridDim.x;  // label-major [k][units]: each label's scan reads one row
   for (int j = threadIdx.x; j < k; j += 64) uh[(size_t)j * units + blockIdx.x] = h[j];

@@ -96,12 +96,10 @@ struct silh_ctx {
   std::vector<double> q_h;
   std::vector<int32_t> f0_off32_h, s_off32_h, sp_off_h, cnt_h, items_h, citem_first_h, citem_count_h;
   std::vector<int64_t> f0_off_h, s_off_h;
-  int bad_h = 0;
   double mean_h = 0.0;
 
   // index
   int32_t* csize = nullptr;  // u32 counts reinterpreted (sizes < 2^31)
-  int* bad = nullptr;
   int32_t* off = nullptr;
   int32_t* uh = nullptr;
   int32_t* perm = nullptr;
@@ -515,7 +513,7 @@ silh_status build_index(silh_ctx* c) {
   const int units = (int)ceil_div(n, seg);
   {
     Carve cv;
-    cv.add(&c->csize, (size_t)k).add(&c->bad, 1).add(&c->off, (size_t)k + 1).add(&c->q, (size_t)k);
+    cv.add(&c->csize, (size_t)k).add(&c->off, (size_t)k + 1).add(&c->q, (size_t)k);
     cv.add(&c->uh, (size_t)units * k).add(&c->perm, (size_t)n).add(&c->slab, (size_t)n);
     if (c->prm.metric == SILH_COS) cv.add(&c->rn, (size_t)n);
     CHK(cv.commit(c, c->alloc_init));
@@ -526,11 +524,12 @@ silh_status build_index(silh_ctx* c) {
     launch_rnorm(c->st, c->X, n, c->d, c->rn);
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
-  // cluster sizes from the sort's per-unit histograms (no separate count pass)
+  // cluster sizes from the sort's per-unit histograms (no separate count pass);
+  // a label outside [0, k) is counted nowhere, so the sizes then sum to less
+  // than n (no flag word to clear and read)
   {
     Launch L(c, K_SORT_HIST);
-    launch_unit_hist(c->st, c->labels, n, k, seg, c->uh, c->bad);
+    launch_unit_hist(c->st, c->labels, n, k, seg, c->uh, nullptr);
     CHK(L.done());
   }
   {
@@ -539,8 +538,12 @@ silh_status build_index(silh_ctx* c) {
     CHK(L.done());
   }
   c->counts_h.assign(k, 0u);
-  CHK(fetch(c, {{c->counts_h.data(), c->csize, k * sizeof(uint32_t)}, {&c->bad_h, c->bad, sizeof(int)}}));
-  if (c->bad_h) return fail(SILH_E_LABEL, "a label lies outside [0, %d)", k);
+  CHK(fetch(c, {{c->counts_h.data(), c->csize, k * sizeof(uint32_t)}}));
+  {
+    uint64_t tot = 0;
+    for (int j = 0; j < k; ++j) tot += c->counts_h[j];
+    if (tot != (uint64_t)n) return fail(SILH_E_LABEL, "a label lies outside [0, %d)", k);
+  }
   c->csize_h.assign(k, 0);
   c->off_h.assign(k + 1, 0);
   int nonempty = 0;
@@ -748,10 +751,9 @@ silh_status phase1(silh_ctx* c, bool host_items = false) {
       if (dist_cap > 0) cv.add(&c->dbase, (size_t)k).add(&c->dkeep, (size_t)dist_cap);
       CHK(cv.commit(c, c->alloc_sample));
     }
-    HIPCHK(hipMemsetAsync(c->p1_status, 0, sizeof(int), c->st));
     launch_f0_items(c->st, c->csize, c->off, c->f0_off, k, c->t, chunk, (int)f0_cap, part_cap, (int)items_cap,
                     c->citem_first, c->citem_count, c->ibase, c->imeta, c->items, c->p1_status, c->dbase,
-                    dist_cap);
+                    dist_cap, true);
     HIPCHK(hipGetLastError());
     {
       Launch L(c, K_F0_PACK);

@@ -24,7 +24,8 @@ constexpr int kP2Rows = 256;
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- cluster index -------------------------------------------------------
-// per-unit label histograms uh [k][units] (label-major); *bad = 1 if a label is outside [0, k)
+// per-unit label histograms uh [k][units] (label-major); *bad = 1 if a label
+// is outside [0, k) (bad may be null: such a label is counted nowhere)
 void launch_unit_hist(hipStream_t st, const int32_t* labels, int n, int k, int seg, int32_t* uh, int* bad);
 // uh[u][j] <- label j's rows before unit u; counts[j] = |C_j|
 void launch_unit_scan(hipStream_t st, int32_t* uh, int units, int k, int32_t* counts);
@@ -198,11 +199,13 @@ void launch_index_sizes(hipStream_t st, const int32_t* csize, int k, double lnte
 // clamps f0_off to f0_cap and writes the W work items (items_cap slots, the
 // unused ones empty), per-cluster first item / count and partial bases;
 // with dbase non-null also the bases of the kept distances (DistStore) and
-// meta[1] = 1 when they fit dist_cap doubles
+// meta[1] = 1 when they fit dist_cap doubles.  The capacity bits go into
+// *status: ORed in, or with assign_status the word is set to them (a status
+// word of its own, which then needs no clear before the launch)
 void launch_f0_items(hipStream_t st, const int32_t* csize, const int32_t* off, int32_t* f0_off, int k,
                      int64_t t, int chunk, int f0_cap, int64_t part_cap, int items_cap, int32_t* citem_first,
                      int32_t* citem_count, int64_t* ibase, int32_t* meta, int32_t* items, int* status,
-                     int64_t* dbase = nullptr, int64_t dist_cap = 0);
+                     int64_t* dbase = nullptr, int64_t dist_cap = 0, bool assign_status = false);
 // capacity (doubles) of the kept distances for n elements, k clusters and
 // ln(5k/delta): about 1.25 times their expected count, at most 2^27
 int64_t dist_capacity(int64_t n, double lnterm);
