@@ -453,6 +453,51 @@ void launch_w_final(hipStream_t st, const int32_t* f0_cl, int F0, const int32_t*
 // ----------------------------------------------------------------------------
 constexpr int kDrawB = 8;  // kept distances loaded together by the draw
 
+// The draw's path for distances the W pass did not keep: the element's row
+// read from memory four coordinates at a time as each chain goes (the same
+// operations in the same order as dist64 on the row held in registers), so
+// that this rarely taken path does not set the draw kernel's register count
+// and occupancy for the kept-distance path.
+__device__ __forceinline__ void load4_row(const float* __restrict__ xr, int c0, int d, bool vec, float (&x)[4]) {
+  if (vec) {
+    const bool in = c0 < d;
+    const float4 v = *(const float4*)(xr + (in ? c0 : 0));
+    x[0] = in ? v.x : 0.0f;
+    x[1] = in ? v.y : 0.0f;
+    x[2] = in ? v.z : 0.0f;
+    x[3] = in ? v.w : 0.0f;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = c0 + e < d ? xr[c0 + e] : 0.0f;
+  }
+}
+
+template <int M, int DM>
+__device__ __forceinline__ double dist64_mem(const float* __restrict__ xr, int d, bool vec, double nx2,
+                                             const double* __restrict__ y) {
+  double acc = 0.0, dot = 0.0, ny2 = 0.0;
+#pragma unroll 2
+  for (int c0 = 0; c0 < DM; c0 += 4) {
+    float x[4];
+    load4_row(xr, c0, d, vec, x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dist64_step<M>(acc, dot, ny2, (double)x[e], y[c0 + e]);
+  }
+  return dist64_final<M>(acc, dot, ny2, nx2);
+}
+
+template <int DM>
+__device__ __forceinline__ double row_norm2_mem(const float* __restrict__ xr, int d, bool vec) {
+  double nx2 = 0.0;
+  for (int c0 = 0; c0 < DM; c0 += 4) {
+    float x[4];
+    load4_row(xr, c0, d, vec, x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) nx2 = nx2 + (double)x[e] * (double)x[e];
+  }
+  return nx2;
+}
+
 template <int M, int DM>
 __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __restrict__ perm,
                                               const int32_t* __restrict__ slab, int n,
@@ -510,8 +555,9 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
     sel = uniform53(seed, (uint64_t)g, kStreamPPS) < p ? 1 : 0;
   } else {
     double gam = 1.0 / (double)m;
-    float x[DM];
-    const double nx2 = load_row<M, DM>(X, d, g, x);
+    const float* xr = X + (size_t)g * d;
+    const bool vec = (d & 3) == 0;
+    const double nx2 = M == kCos ? row_norm2_mem<DM>(xr, d, vec) : 0.0;
     // Most waves lie inside one cluster (sorted order): then the initial
     // sample rows and weights are wave-uniform and come in by scalar loads.
     const int jf = __builtin_amdgcn_readfirstlane(j);
@@ -519,7 +565,7 @@ __global__ __launch_bounds__(256) void k_draw(int sampler, const int32_t* __rest
       const int fb = f0_off[jj], fe = f0_off[jj + 1];
       for (int e = fb; e < fe; ++e) {
         const double w = W[e];
-        const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)e * DM);
+        const double dv = dist64_mem<M, DM>(xr, d, vec, nx2, f0X + (size_t)e * DM);
         if (w > 0.0) {
           const double r = dv / w;
           gam = r > gam ? r : gam;
