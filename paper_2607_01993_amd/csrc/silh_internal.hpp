@@ -75,6 +75,9 @@ void launch_fill_all(hipStream_t st, const int32_t* perm, int n, double* p_gid, 
 // rn[i] = 1 / |X_i| in float32 (fused chain in coordinate order, correctly
 // rounded square root and division), 0 for a zero row
 void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn);
+// the launch_pack mode of a metric (metric ids as in silh_metric: 1 cosine,
+// 3 Canberra)
+inline int pack_mode(int metric) { return metric == 1 ? 1 : (metric == 3 ? 2 : 0); }
 // Scatter the selected elements into the cluster-blocked, padded sample.
 // mode 0: raw coordinates; 1: rows times rn (unit L2 norm, cosine); 2: raw
 // coordinates with aux32 = 1 for a row holding a coordinate of magnitude
@@ -82,8 +85,6 @@ void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn);
 // or past `cap` (the capacity of the packed arrays) are not written.  Every
 // other row in [0, sp_off[k]) is written, the padding rows of each cluster
 // block as id -1 with zero weight, aux and coordinates: no prior clear.
-// the launch_pack mode of a metric
-inline int pack_mode(int metric) { return metric == 1 ? 1 : (metric == 3 ? 2 : 0); }
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
                  const int32_t* pos, int n, int k, const float* X, int d, int DM, const double* p_gid,
                  const int32_t* s_off, const int32_t* sp_off, int mode, const float* rn, int cap,
