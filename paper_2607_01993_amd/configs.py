@@ -1,7 +1,7 @@
 """Phase-2 measurements on each workload shape, with the roofline that bounds
 each path.
 
-    python -m paper_2607_01993_amd.configs [--out FILE]
+    python -m paper_2607_01993_amd.configs [--out FILE] [--only zipf,d256] [--metrics canb,manh]
 
 Workloads (seeded, synthetic):
   small       n = 2,000, d = 8, k = 4 Gaussian blobs, t = 64
@@ -68,7 +68,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--skip-directional", action="store_true")
+    ap.add_argument("--only", default=None, help="comma-separated workloads (small, zipf, sweep-k64, d256, directional)")
+    ap.add_argument("--metrics", default=None, help="comma-separated metrics to measure (default: all)")
     args = ap.parse_args()
+    only = set(args.only.split(",")) if args.only else None
+    mets = set(args.metrics.split(",")) if args.metrics else None
+
+    def want(workload, metric=None):
+        return (only is None or workload in only) and (metric is None or mets is None or metric in mets)
     import torch
 
     from . import native, synth
@@ -77,29 +84,37 @@ def main():
         return torch.from_numpy(X).cuda(), torch.from_numpy(L).cuda()
 
     rows = []
-    X, L = dev(*synth.config_small())
-    for metric, prec in (("eucl", "fp32"), ("eucl", "bf16")):
-        rows.append({"workload": "small", **measure(native, X, L, 4, metric, prec, 64)})
-    X, L = dev(*synth.config_zipf_gauss())
-    for metric, prec in (("eucl", "bf16"), ("eucl", "fp32"), ("cos", "bf16"), ("manh", "fp32"), ("canb", "fp32")):
-        rows.append({"workload": "zipf", **measure(native, X, L, 16, metric, prec, 256)})
-    log("zipf done")
-    del X, L
-    Xe = synth.config_sweep()
-    cen = synth.voronoi_centers(Xe.shape[0], 64, (3, 64))
-    Le = synth.voronoi_labels(Xe, cen)
-    X, L = dev(Xe, Le)
-    for metric, prec in (("eucl", "bf16"), ("canb", "fp32")):
-        rows.append({"workload": "sweep-k64", **measure(native, X, L, 64, metric, prec, 128)})
-    log("sweep-k64 done")
-    n = 500_000
-    Xg, Lg = synth.gaussian_blobs(n, 256, 16, seed=9, sizes=synth.zipf_sizes(n, 16), sigma=(0.5, 2.0))
-    X, L = dev(Xg, Lg)
-    for metric, prec in (("eucl", "bf16"), ("cos", "fp8"), ("manh", "fp32")):
-        rows.append({"workload": "d256", **measure(native, X, L, 16, metric, prec, 256, reps=3)})
-    log("d256 done")
-    del X, L
-    if not args.skip_directional:
+    if want("small"):
+        X, L = dev(*synth.config_small())
+        for metric, prec in (("eucl", "fp32"), ("eucl", "bf16")):
+            if want("small", metric):
+                rows.append({"workload": "small", **measure(native, X, L, 4, metric, prec, 64)})
+    if want("zipf"):
+        X, L = dev(*synth.config_zipf_gauss())
+        for metric, prec in (("eucl", "bf16"), ("eucl", "fp32"), ("cos", "bf16"), ("manh", "fp32"), ("canb", "fp32")):
+            if want("zipf", metric):
+                rows.append({"workload": "zipf", **measure(native, X, L, 16, metric, prec, 256)})
+        log("zipf done")
+        del X, L
+    if want("sweep-k64"):
+        Xe = synth.config_sweep()
+        cen = synth.voronoi_centers(Xe.shape[0], 64, (3, 64))
+        Le = synth.voronoi_labels(Xe, cen)
+        X, L = dev(Xe, Le)
+        for metric, prec in (("eucl", "bf16"), ("canb", "fp32")):
+            if want("sweep-k64", metric):
+                rows.append({"workload": "sweep-k64", **measure(native, X, L, 64, metric, prec, 128)})
+        log("sweep-k64 done")
+    if want("d256"):
+        n = 500_000
+        Xg, Lg = synth.gaussian_blobs(n, 256, 16, seed=9, sizes=synth.zipf_sizes(n, 16), sigma=(0.5, 2.0))
+        X, L = dev(Xg, Lg)
+        for metric, prec in (("eucl", "bf16"), ("cos", "fp8"), ("manh", "fp32")):
+            if want("d256", metric):
+                rows.append({"workload": "d256", **measure(native, X, L, 16, metric, prec, 256, reps=3)})
+        log("d256 done")
+        del X, L
+    if not args.skip_directional and want("directional", "cos"):
         Xv, Lv = synth.config_vmf_cos()
         log("directional data ready")
         X, L = dev(Xv, Lv)
