@@ -48,7 +48,8 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // fp8 (OCP e4m3) path, cosine only: operands are 64 (x~ - y~ components of
 // unit vectors lie in [-2, 2], so |64 v| <= 128 < 448) times the centred
-// coordinates; the squared norms enter through the accumulator input.  The
+// coordinates; the squared norms enter through the accumulator input (with
+// elements as rows the sample's through the clamp bounds instead, kF8R).  The
 // norms are those of the unrounded float32 coordinates, not of the e4m3
 // operands: with c = |x~|^2/2 + |y~|^2/2 - x~_q.y~_q the rounding error of
 // each pair is first order in the operand errors (x~.dy + dx.y~), whose sum
@@ -573,7 +574,8 @@ __device__ __forceinline__ void load_tile(const void* __restrict__ Ym, const flo
 // without the recompute path, which must not lower it)
 // (two tiles per LDS stage hold enough LDS to set the occupancy themselves)
 template <int M, int P, int DM, int PB, int TBX>
-constexpr int kMinWaves = (M != kEucl || P == 2 || PB == 2 || DM < 32 || (TBX == 2 && MCfg<P, DM>::LDS)) ? 1
+constexpr int kMinWaves = (P == 2 && DM == 128) ? 2
+                          : (M != kEucl || P == 2 || PB == 2 || DM < 32 || (TBX == 2 && MCfg<P, DM>::LDS)) ? 1
                           : DM == 32 ? (P == 1 ? 4 : 1) : DM == 64 ? 3 : DM == 128 ? 2 : 1;
 
 // One block of the Phase-2 launch: 4 waves x PB x 32 elements, from element
@@ -720,6 +722,15 @@ __device__ __forceinline__ void p2_mfma_block(
   // fp8: 64^2 (alpha |x~_q|^2 + u_x) of this lane's element (kT), of its
   // 16 accumulator rows (element-row layout)
   float nxc[PB][kT ? 1 : 16];
+  // fp8 with element rows (the pipelined path): the element terms as the
+  // MFMA's accumulator input (the same every tile of a cluster); the sample
+  // term 64^2 |y~|^2 / 2 of column col shifts the clamp instead,
+  //   med3(c + v, 0, 2 S2) = med3(c, -v, 2 S2 - v) + v,
+  // and its weighted sum, the same for every element, goes into tcol (per
+  // lane column, added to every element's sum at the fold)
+  constexpr bool kF8R = P == 2 && !kT;
+  f32x16 nxv[PB];
+  float tcol[PB];
   int thrx[PB];   // Euclidean: the element's recompute threshold (float bits, >= 0)
   int chk[PB];    // Euclidean: some element of the block may meet the threshold (wave-uniform, 0 / 1)
   // The packed cluster blocks are contiguous, so the tile after a cluster's
@@ -832,7 +843,7 @@ __device__ __forceinline__ void p2_mfma_block(
         } else {
           // the C rows of this lane are elements 8(r/4) + 4h + r%4 of the block
 #pragma unroll
-          for (int r = 0; r < 16; ++r) nxc[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
+          for (int r = 0; r < 16; ++r) nxv[b][r] = __shfl(rowv, 8 * (r >> 2) + 4 * h + (r & 3), kWave);
         }
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s)
@@ -907,6 +918,7 @@ __device__ __forceinline__ void p2_mfma_block(
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       wsum[b] = 0.0;
+      tcol[b] = 0.f;
 #pragma unroll
       for (int r = 0; r < kNA; ++r) acc[b][r] = 0.f;
     }
@@ -935,9 +947,7 @@ __device__ __forceinline__ void p2_mfma_block(
           c[r] = nxc[b][0] + row_val<r>(v0, v1);
         });
       } else {
-        const float bcol = S2 * __int_as_float(gv[0]);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) c[r] = nxc[b][r] + bcol;
+        c = nxv[b];  // the sample term is in the clamp bounds (kF8R)
       }
     };
     auto chain = [&](auto&& getB, const int (&gv)[2], f32x16 (&cc)[PB]) {
@@ -1055,6 +1065,11 @@ __device__ __forceinline__ void p2_mfma_block(
         for (int r = 0; r < 16; ++r) dv[r] = dist(cc[b][r]);
         if constexpr (kT) {
           wsum16(acc[b], wv[0], wv[1], dv);
+        } else if constexpr (kF8R) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            acc[b][r] = fmaf(wv[0], __builtin_amdgcn_fmed3f(cc[b][r], -wv[1], 2.0f * S2 - wv[1]), acc[b][r]);
+          tcol[b] = fmaf(wv[0], wv[1], tcol[b]);
         } else {
 #pragma unroll
           for (int r = 0; r < 16; ++r) acc[b][r] = fmaf(wv[0], dv[r], acc[b][r]);
@@ -1071,8 +1086,17 @@ __device__ __forceinline__ void p2_mfma_block(
             v = lane_sum(acc[b]);
           else
             v = transpose_reduce16(acc[b], lane);
-          // fp8: the distances came scaled by 64^2 (a power of two)
-          wsum[b] += P == 2 ? (double)v * (1.0 / S2) : (double)v;
+          if constexpr (kF8R) {
+            // the sample terms' sum over the 32 columns (the same in both halves)
+            float t = tcol[b];
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) t += __shfl_xor(t, o, kWave);
+            wsum[b] += ((double)v + (double)t) * (1.0 / S2);
+            tcol[b] = 0.f;
+          } else {
+            // fp8: the distances came scaled by 64^2 (a power of two)
+            wsum[b] += P == 2 ? (double)v * (1.0 / S2) : (double)v;
+          }
 #pragma unroll
           for (int r = 0; r < kNA; ++r) acc[b][r] = 0.f;
         }
@@ -1104,6 +1128,9 @@ __device__ __forceinline__ void p2_mfma_block(
 #pragma unroll
         for (int r = 0; r < 16; ++r) c[r] = 0.0f;
       }
+      // fp8: the pending tile's clamp bounds and its sample-term sum
+      const float plo = -wp[1], phi = 2.0f * S2 - wp[1];
+      if constexpr (kF8R) tcol[0] = fmaf(wp[0], wp[1], tcol[0]);
       __builtin_amdgcn_sched_barrier(0);
       static_for<NS>([&](auto QC) {
         constexpr int q = decltype(QC)::value;
@@ -1118,7 +1145,8 @@ __device__ __forceinline__ void p2_mfma_block(
         for (int mi = 0; mi < kDw; ++mi)
           if (q == (2 * mi + 1) * NS / (2 * kDw)) tile_load(tt, mi);
 #pragma unroll
-        for (int r = 16 * q / NS; r < 16 * (q + 1) / NS; ++r) acc[0][r] = fmaf(wp[0], dist(cp[0][r]), acc[0][r]);
+        for (int r = 16 * q / NS; r < 16 * (q + 1) / NS; ++r)
+          acc[0][r] = fmaf(wp[0], kF8R ? __builtin_amdgcn_fmed3f(cp[0][r], plo, phi) : dist(cp[0][r]), acc[0][r]);
         __builtin_amdgcn_sched_barrier(0);
       });
       cn[0] = c;
@@ -1178,6 +1206,8 @@ __device__ __forceinline__ void p2_mfma_block(
             wv[1] = *(const float*)(tb + (wr + 16) * kLRow);
           } else {
             wv[0] = *(const float*)(tb + col * kLRow);
+            // fp8: the sample term 64^2 |y~|^2 / 2 of the lane's column
+            if constexpr (kF8R) wv[1] = S2 * *(const float*)(tb + 4 + col * kLRow);
           }
         };
         auto gval = [&](int tt, int (&gv)[2]) {
@@ -1219,6 +1249,7 @@ __device__ __forceinline__ void p2_mfma_block(
 #pragma unroll
             for (int b = 0; b < PB; ++b) ca[b] = cb[b];
             wa[0] = wb[0];
+            wa[1] = wb[1];
           }
         } else {
 #pragma unroll
