@@ -45,7 +45,7 @@ WORKLOAD = dict(n=1_000_000, d=32, k=16, t=256, seed=1)
 # runs (FETCH_SIZE, WRITE_SIZE; scaled by a 256 MiB copy), valid only for the
 # kernel source they were taken with (sha256 prefix of the source file).
 TRAFFIC = {
-    ("eucl", "bf16"): {"src": "paper_2607_01993_amd/csrc/k_phase2_mfma.hip", "sha256": "8cbc7d3b624e512c",
+    ("eucl", "bf16"): {"src": "paper_2607_01993_amd/csrc/k_phase2_mfma.hip", "sha256": "9991418b0ee7ddce",
                        "bytes": (136.7 + 12.3) * 1e6,
                        "profile": "profiles/hbm_traffic_zipf_n1e6_d32_k16_t256.md"},
 }
