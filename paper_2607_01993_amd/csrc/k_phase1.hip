@@ -770,29 +770,49 @@ __global__ __launch_bounds__(256) void k_pack(const int32_t* __restrict__ perm,
 // Reciprocal L2 norm of every row in float32 (one rounding per operation:
 // a fused multiply-add chain in coordinate order, then a correctly rounded
 // square root and division), 0 for a zero row.  The cosine kernels scale both
-// the element rows and the packed sample rows by it.
+// the element rows and the packed sample rows by it.  A block takes
+// kRnRows rows: the 256 threads read them kRnCols columns at a time,
+// coalesced, into LDS (row stride kRnCols + 1, so the chains below read
+// distinct banks), and thread r < kRnRows carries row r's chain.  A row's
+// value depends on nothing but its own coordinates.
+constexpr int kRnRows = 64, kRnCols = 128;
+
 __global__ __launch_bounds__(256) void k_rnorm(const float* __restrict__ X, int n, int d, float* __restrict__ rn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float* xr = X + (size_t)i * d;
+  __shared__ float tile[kRnRows][kRnCols + 1];
+  const int64_t row0 = (int64_t)blockIdx.x * kRnRows;
+  const int nr = n - row0 < kRnRows ? (int)(n - row0) : kRnRows;
+  const bool vec = (d & 3) == 0 && ((uintptr_t)X & 15) == 0;
   float s2 = 0.0f;
-  if ((d & 3) == 0 && ((uintptr_t)X & 15) == 0) {
-    for (int c = 0; c < d; c += 4) {
-      const float4 v = *(const float4*)(xr + c);
-      s2 = fmaf(v.x, v.x, s2);
-      s2 = fmaf(v.y, v.y, s2);
-      s2 = fmaf(v.z, v.z, s2);
-      s2 = fmaf(v.w, v.w, s2);
+  for (int c0 = 0; c0 < d; c0 += kRnCols) {
+    const int cw = d - c0 < kRnCols ? d - c0 : kRnCols;
+    if (vec) {
+      const int q4 = cw >> 2;  // float4 per row of the chunk
+      for (int q = threadIdx.x; q < nr * q4; q += 256) {
+        const int r = q / q4, c = (q - r * q4) << 2;
+        const float4 v = *(const float4*)(X + (row0 + r) * d + c0 + c);
+        tile[r][c] = v.x;
+        tile[r][c + 1] = v.y;
+        tile[r][c + 2] = v.z;
+        tile[r][c + 3] = v.w;
+      }
+    } else {
+      for (int q = threadIdx.x; q < nr * cw; q += 256) {
+        const int r = q / cw, c = q - r * cw;
+        tile[r][c] = X[(row0 + r) * d + c0 + c];
+      }
     }
-  } else {
-    for (int c = 0; c < d; ++c) s2 = fmaf(xr[c], xr[c], s2);
+    __syncthreads();
+    if (threadIdx.x < nr) {
+      for (int c = 0; c < cw; ++c) s2 = fmaf(tile[threadIdx.x][c], tile[threadIdx.x][c], s2);
+    }
+    __syncthreads();
   }
-  rn[i] = s2 > 0.0f ? 1.0f / sqrtf(s2) : 0.0f;
+  if (threadIdx.x < nr) rn[row0 + threadIdx.x] = s2 > 0.0f ? 1.0f / sqrtf(s2) : 0.0f;
 }
 
 void launch_rnorm(hipStream_t st, const float* X, int n, int d, float* rn) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_rnorm, dim3((int)ceil_div(n, 256)), dim3(256), 0, st, X, n, d, rn);
+  hipLaunchKernelGGL(k_rnorm, dim3((int)ceil_div(n, kRnRows)), dim3(256), 0, st, X, n, d, rn);
 }
 
 void launch_pack(hipStream_t st, const int32_t* perm, const int32_t* slab, const int32_t* flag,
