@@ -129,10 +129,12 @@ __device__ __forceinline__ void load_chunk_wide(const float* __restrict__ xr, in
   }
 }
 
-// the squared norm of a streamed row, in coordinate order (cosine)
+// the squared norm of a streamed row, in coordinate order (cosine; DW is
+// the padded width, the coordinates past d add exact zeros)
+template <int DW = kWideDM>
 __device__ __forceinline__ double row_norm2_wide(const float* __restrict__ xr, int d, bool vec) {
   double nx2 = 0.0;
-  for (int c0 = 0; c0 < kWideDM; c0 += kWideC) {
+  for (int c0 = 0; c0 < DW; c0 += kWideC) {
     float x[kWideC];
     load_chunk_wide(xr, d, c0, vec, x);
 #pragma unroll
@@ -142,14 +144,14 @@ __device__ __forceinline__ double row_norm2_wide(const float* __restrict__ xr, i
 }
 
 // distances from row xr to the kWideG rows ys[e][.] (stride kWideDM)
-template <int M>
+template <int M, int DW = kWideDM>
 __device__ __forceinline__ void dist64_group_wide(const float* __restrict__ xr, int d, bool vec, double nx2,
                                                   const double (*__restrict__ ys)[kWideDM],
                                                   double (&dv)[kWideG]) {
   double acc[kWideG], dot[kWideG], ny2[kWideG];
 #pragma unroll
   for (int e = 0; e < kWideG; ++e) acc[e] = dot[e] = ny2[e] = 0.0;
-  for (int c0 = 0; c0 < kWideDM; c0 += kWideC) {
+  for (int c0 = 0; c0 < DW; c0 += kWideC) {
     float x[kWideC];
     load_chunk_wide(xr, d, c0, vec, x);
 #pragma unroll
@@ -258,6 +260,7 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
                                                    const float* __restrict__ X, int d,
                                                    const double* __restrict__ f0X,
                                                    double* __restrict__ partial, DistStore ds) {
+  static_assert(DM <= 64, "longer rows take k_w_partial_wide");
   __shared__ double sh[4][kWSlots];  // per wave, per initial element of the current batch
   const int32_t* it = items + (size_t)blockIdx.x * 6;
   const int begin = it[1], end = it[2], f0b = it[3], f0n = it[4], pb = it[5];
@@ -281,24 +284,6 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
   } else {
 #pragma unroll
     for (int c = 0; c < DM; ++c) x[c] = 0.0f;
-  }
-  if constexpr (DM > 64) {
-    // long rows: one block sum per initial element (the batched form below
-    // does not fit the registers next to a 128-float row)
-    for (int e0 = 0; e0 < f0n; e0 += kEB) {
-      const int ne = f0n - e0 < kEB ? f0n - e0 : kEB;
-#pragma unroll
-      for (int e = 0; e < kEB; ++e) {
-        const int ee = e < ne ? e : ne - 1;   // repeats a row instead of branching
-        const double dv = dist64<M, DM>(x, nx2, f0X + (size_t)(f0b + e0 + ee) * DM);
-        if (e < ne) {  // ne is uniform over the block
-          if (keep != nullptr && have) keep[(int64_t)(e0 + e) * kstride] = dv;
-          const double tot = block_sum_f64<256>(have ? dv : 0.0, &sh[0][0]);
-          if (threadIdx.x == 0) partial[pb + e0 + e] = tot;
-        }
-      }
-    }
-    return;
   }
   // per initial element: member distances summed over the wave, then the
   // four wave sums in wave order (one thread per element)
@@ -328,9 +313,11 @@ __global__ __launch_bounds__(256) void k_w_partial(const int32_t* __restrict__ i
   }
 }
 
-// d > 128: a 256-thread block per item (one member per thread), the item's
-// initial-sample rows staged kWideG at a time
-template <int M>
+// d > 64: a 256-thread block per item (one member per thread), each thread
+// streaming its row from memory, the item's initial-sample rows (stride DW)
+// staged kWideG at a time.  At d <= 128 the row would fit the registers, but
+// beside the float64 chains of k_w_partial it leaves one wave per SIMD
+template <int M, int DW>
 __global__ __launch_bounds__(256) void k_w_partial_wide(const int32_t* __restrict__ items,
                                                         const int32_t* __restrict__ perm,
                                                         const float* __restrict__ X, int d,
@@ -351,17 +338,17 @@ __global__ __launch_bounds__(256) void k_w_partial_wide(const int32_t* __restric
   const bool have = r < end;
   const float* xr = X + (size_t)(have ? perm[r] : 0) * d;
   const bool vec = (d & 3) == 0 && ((uintptr_t)X & 15) == 0;
-  const double nx2 = M == kCos ? row_norm2_wide(xr, d, vec) : 0.0;
+  const double nx2 = M == kCos ? row_norm2_wide<DW>(xr, d, vec) : 0.0;
   for (int e0 = 0; e0 < f0n; e0 += kWideG) {
     const int ne = f0n - e0 < kWideG ? f0n - e0 : kWideG;  // uniform over the block
     __syncthreads();
-    for (int q = threadIdx.x; q < kWideG * kWideDM; q += 256) {
-      const int e = q / kWideDM, c = q - e * kWideDM;
-      ys[e][c] = f0X[(size_t)(f0b + e0 + (e < ne ? e : ne - 1)) * kWideDM + c];  // past ne: a copy
+    for (int q = threadIdx.x; q < kWideG * DW; q += 256) {
+      const int e = q / DW, c = q - e * DW;
+      ys[e][c] = f0X[(size_t)(f0b + e0 + (e < ne ? e : ne - 1)) * DW + c];  // past ne: a copy
     }
     __syncthreads();
     double dv[kWideG];
-    dist64_group_wide<M>(xr, d, vec, nx2, ys, dv);
+    dist64_group_wide<M, DW>(xr, d, vec, nx2, ys, dv);
 #pragma unroll
     for (int e = 0; e < kWideG; ++e) {
       if (e < ne) {
@@ -403,8 +390,16 @@ void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, 
                       const int32_t* perm, const float* X, int d, const double* f0X, double* partial,
                       DistStore ds) {
   if (nitems <= 0) return;
-  if (DM == kWideDM) {
-#define SILH_WP(MM) hipLaunchKernelGGL(k_w_partial_wide<MM>, dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial, ds)
+  if (DM == kWideDM || DM == 128) {
+#define SILH_WP(MM)                                                                                       \
+  do {                                                                                                    \
+    if (DM == 128)                                                                                        \
+      hipLaunchKernelGGL((k_w_partial_wide<MM, 128>), dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, \
+                         partial, ds);                                                                    \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_w_partial_wide<MM, kWideDM>), dim3(nitems), dim3(256), 0, st, items, perm, X, d, \
+                         f0X, partial, ds);                                                               \
+  } while (0)
     switch (metric) {
       case kEucl: SILH_WP(kEucl); break;
       case kCos: SILH_WP(kCos); break;
@@ -414,7 +409,19 @@ void launch_w_partial(hipStream_t st, int metric, int DM, const int32_t* items, 
 #undef SILH_WP
     return;
   }
-  SILH_P1_DISPATCH(k_w_partial, dim3(nitems), items, perm, X, d, f0X, partial, ds);
+  // DM <= 64 here (the row in registers beside the float64 chains)
+  switch (metric * 8 + (DM == 8 ? 0 : DM == 16 ? 1 : DM == 32 ? 2 : 3)) {
+#define SILH_WPS(CASE, MM, DD)                                                                            \
+  case CASE:                                                                                              \
+    hipLaunchKernelGGL((k_w_partial<MM, DD>), dim3(nitems), dim3(256), 0, st, items, perm, X, d, f0X, partial, ds); \
+    break;
+    SILH_WPS(0, kEucl, 8) SILH_WPS(1, kEucl, 16) SILH_WPS(2, kEucl, 32) SILH_WPS(3, kEucl, 64)
+    SILH_WPS(8, kCos, 8) SILH_WPS(9, kCos, 16) SILH_WPS(10, kCos, 32) SILH_WPS(11, kCos, 64)
+    SILH_WPS(16, kManh, 8) SILH_WPS(17, kManh, 16) SILH_WPS(18, kManh, 32) SILH_WPS(19, kManh, 64)
+    SILH_WPS(24, kCanb, 8) SILH_WPS(25, kCanb, 16) SILH_WPS(26, kCanb, 32)
+    default: SILH_WPS(27, kCanb, 64)
+#undef SILH_WPS
+  }
 }
 
 // W(e_bar): sum of its cluster's item partials.  One block per initial
